@@ -1,0 +1,186 @@
+/*
+ * xcorr.h -- C ABI of the MI355X (gfx950) FX correlator for space VLBI.
+ *
+ * The correlator implements the FX architecture the paper describes for the
+ * DiFX software correlator (abstract: Fourier transform first, then
+ * cross-multiply), extended as in section 2 for a space antenna: each
+ * station's delay comes from a per-scan polynomial that already contains the
+ * space-specific terms (arbitrary moving position and velocity, relativistic
+ * corrections, and the spacecraft-to-tracking-station transmission delay),
+ * and the station data arrive in a Mark5B-style recording (section 2, format
+ * conversion paragraph).  Per station and FFT frame the library
+ *   1. evaluates the delay polynomial in FP64 at the frame centre, splitting
+ *      the delay into an integer sample shift and a fractional part,
+ *   2. unpacks the 2-bit samples of the shifted window,
+ *   3. rotates each sample by the fringe phase exp(+2 pi i phi(t_n)),
+ *   4. FFTs the frame to channels (kept: DC .. Nyquist-1),
+ *   5. corrects the fractional delay per channel, Y[k] *= exp(+2 pi i k d / N),
+ * and then cross-multiplies every pair of inputs i <= j of a subband and
+ * accumulates V_ij[k] = mean over frames of Y_i[k] conj(Y_j[k]).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers documented as "device" must point to memory of the context's
+ *     HIP device; "host" pointers are read during the call only.
+ *   - The caller owns every input, output and workspace buffer.  The library
+ *     owns only the context (and servers); it allocates device memory only in
+ *     xc_create and xc_server_create, never on the correlation path.
+ *   - Calls that take a stream are asynchronous on that stream (a HIP stream
+ *     handle cast to void*, NULL for the default stream) unless stated.
+ *   - Return codes: XC_OK (0) or a negative XC_E_* value; xc_last_error()
+ *     gives a message for the last failure on the context.  Frames whose
+ *     window leaves the recording or touches a recording frame with a bad sync
+ *     word are not errors: they get weight 0 (see xc_output.weight).
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef XCORR_H
+#define XCORR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define XC_OK           0
+#define XC_E_INVAL     -1   /* bad shape, non-power-of-two channels, stream map out of range */
+#define XC_E_RANGE     -2   /* sub-integration outside a polynomial's validity span */
+#define XC_E_NOMEM     -3   /* workspace too small, or a server cannot admit the job */
+#define XC_E_HIP       -4   /* a HIP runtime call failed */
+#define XC_E_CANCELLED -5
+#define XC_E_TIMEOUT   -6
+
+#define XC_FP32        0    /* FP32 fringe rotation, FFT and cross-multiply */
+#define XC_FP16_MFMA   1    /* X step on MFMA, FP16 inputs, FP32 accumulate */
+#define XC_FP8_MFMA    2    /* X step on MFMA, FP8 (e4m3) inputs, FP32 accumulate */
+
+#define XC_MAX_POLY_DEG   7
+#define XC_MAX_STATIONS   64
+#define XC_MAX_SUBBANDS   16
+#define XC_MAX_INPUTS     32   /* n_subbands * n_pols per station */
+#define XC_MIN_CHAN       128
+#define XC_MAX_CHAN       16384
+
+/* Recording format: frames of 10016 bytes = 16-byte header (uint32 words:
+ * 0xABADDEED sync, frame-in-second | station id << 16, integer second, 0)
+ * + 2500 little-endian uint32 payload words.  With C recorded streams each
+ * payload word holds 16 two-bit fields; field j (bits 2j..2j+1) is stream
+ * j mod C at per-stream sample word*(16/C) + j/C, counting payload words from
+ * the start of the recording.  Codes 0..3 are the levels -3.3359, -1, +1,
+ * +3.3359 (offset binary). */
+#define XC_FRAME_BYTES    10016
+#define XC_SYNC_WORD      0xABADDEEDu
+
+/* ---------------------------------------------------------------- context */
+typedef struct xc_ctx xc_ctx;
+
+/* Create a context on HIP device `hip_device`; uploads the FFT twiddle table.
+ * Returns XC_OK and sets *out, or XC_E_HIP / XC_E_INVAL. */
+int  xc_create(xc_ctx** out, int hip_device);
+void xc_destroy(xc_ctx* ctx);
+/* Static message for a return code. */
+const char* xc_strerror(int code);
+/* Detail of the last failure on this context (empty string if none). */
+const char* xc_last_error(const xc_ctx* ctx);
+
+/* ---------------------------------------------------------------- job description */
+typedef struct {
+  int32_t n_stations;          /* S, 1..XC_MAX_STATIONS */
+  int32_t n_subbands;          /* 1..XC_MAX_SUBBANDS */
+  int32_t n_pols;              /* P, 1 or 2; inputs are ordered i = s*P + p */
+  int32_t n_chan;              /* channels kept; FFT length N = 2*n_chan, power of two */
+  int32_t n_streams_recorded;  /* C in {1,2,4,8,16} */
+  const int32_t* stream_map;   /* host [n_subbands*n_pols]: input (sb,p) -> recorded stream */
+  double  fs_hz;               /* per-stream sample rate (twice the bandwidth, real sampling) */
+  const double* lo_hz;         /* host [n_subbands]: sky frequency of each band's lower edge */
+  int64_t sub_start;           /* reference-time sample index of the sub-integration start */
+  int64_t n_frames;            /* FFT frames in the sub-integration (>= 1) */
+  int32_t precision;           /* XC_FP32 | XC_FP16_MFMA | XC_FP8_MFMA */
+  int32_t frames_per_block;    /* frames staged per F/X round, 0 = library's choice (<= 256) */
+} xc_setup;
+
+typedef struct {
+  const void*    frames;       /* device: the station's recording, n_frames_m5b frames */
+  int64_t        n_frames_m5b;
+  int64_t        first_sample; /* station-time sample index of the first payload sample */
+  const uint8_t* frame_ok;     /* device [n_frames_m5b] from xc_ingest, or NULL (computed) */
+  int32_t        poly_deg;     /* 0..XC_MAX_POLY_DEG */
+  const double*  delay_poly;   /* host [poly_deg+1]: tau(t) in seconds, ascending powers,
+                                  t = reference time in seconds since the polynomial epoch */
+  const double*  phase_poly;   /* host [n_subbands][poly_deg+1] fringe phase in turns of the
+                                  same t, or NULL: phase = lo_hz[sb] * tau(t) */
+  double         poly_t0, poly_t1;  /* validity span of the polynomials (seconds) */
+} xc_station;
+
+typedef struct {
+  void*  vis;      /* device: complex float [n_subbands][M(M+1)/2][n_chan], M = S*P;
+                      baselines (i,j), i <= j, packed row-major, diagonal = autos */
+  float* weight;   /* device: float [n_subbands][M(M+1)/2], frames valid for both inputs */
+} xc_output;
+
+/* ---------------------------------------------------------------- ingest (A0) */
+/* Per-frame validity of a recording: frame_ok[f] = 1 iff frame f's sync word is
+ * 0xABADDEED.  frames: device, n_frames_m5b * 10016 bytes; frame_ok: device.  Async. */
+int xc_ingest(xc_ctx* ctx, const void* frames, int64_t n_frames_m5b, uint8_t* frame_ok,
+              void* stream);
+
+/* ---------------------------------------------------------------- plain per-job path */
+/* Check a job description without touching the GPU: XC_OK, XC_E_INVAL or
+ * XC_E_RANGE (message in xc_last_error when ctx is not NULL). */
+int xc_validate(xc_ctx* ctx, const xc_setup* setup, const xc_station* st);
+
+/* Device workspace a correlate_subint call with this setup needs (0 on bad setup). */
+size_t xc_workspace_bytes(const xc_ctx* ctx, const xc_setup* setup, const xc_station* st);
+
+/* Correlate one sub-integration.  st: host [n_stations]; out: host struct of
+ * device pointers; workspace: device, ws_bytes >= xc_workspace_bytes().  Async
+ * on `stream`; results are complete when the stream reaches this point.
+ * V = mean over valid frames (unnormalised FFT); W = 0 gives V = 0. */
+int xc_correlate_subint(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
+                        const xc_output* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- test taps */
+/* Same kernels as the correlation path, results copied to host; synchronous. */
+/* Delay model per station and frame: n_int [S][F], d_frac [S][F], valid [S][F],
+ * phi0 [S][n_subbands][F] (fringe phase at the frame centre, turns in [0,1)).
+ * Any output pointer may be NULL. */
+int xc_debug_delays(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
+                    int64_t* n_int, double* d_frac, int32_t* valid, double* phi0,
+                    void* workspace, size_t ws_bytes, void* stream);
+/* Unpacked levels q[n] (float, host [N]) of input `input` (= sb*P + p) of
+ * station `station` for frame `frame`, after the integer shift; all zero if
+ * the frame is invalid. */
+int xc_debug_unpack(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
+                    int32_t station, int32_t input, int64_t frame, float* out,
+                    void* workspace, size_t ws_bytes, void* stream);
+/* Spectra after fractional-delay correction for frames frame0 .. frame0+n-1
+ * (n <= frames_per_block of the setup): device complex float
+ * [n_subbands][n][M][n_chan].  Async. */
+int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
+                     int64_t frame0, int32_t n, void* spectra, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- kernel timing */
+/* Kernel kinds for xc_profile_end. */
+#define XC_K_INGEST    0
+#define XC_K_DELAYS    1
+#define XC_K_FSTAGE    2
+#define XC_K_XMAC      3
+#define XC_K_XMFMA     4
+#define XC_K_FINALISE  5
+#define XC_K_ZERO      6
+#define XC_NKINDS      7
+
+/* Start recording a HIP event pair around every kernel launch of this context
+ * (on the launch's own stream), for at most max_launches launches. */
+int xc_profile_begin(xc_ctx* ctx, int32_t max_launches);
+/* Stop recording, wait for the recorded events and return, per kind, the
+ * summed kernel time in ms and the launch count (host arrays [XC_NKINDS]).
+ * Synchronous. */
+int xc_profile_end(xc_ctx* ctx, double* ms_by_kind, int64_t* launches_by_kind);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XCORR_H */

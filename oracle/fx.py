@@ -202,18 +202,37 @@ def baseline_index(i: int, j: int, M: int) -> int:
     return i * M - i * (i - 1) // 2 + (j - i)
 
 
+
+def _partial_sums(job, sb, ins, fc, words, rotate, frac, full_band):
+    """O9 over one chunk of frames: (sum of Y_a conj(Y_b) [m, m, K], pair counts [m, m])."""
+    P = job.n_pols
+    Ys, vs = [], []
+    for i in ins:
+        Y, v = station_spectra(job, i // P, sb, i % P, fc, rotate=rotate, frac=frac,
+                               full_band=full_band, words=words[i // P])
+        Ys.append(Y)
+        vs.append(v)
+    Ya = np.stack(Ys)                                              # [m, nf, K]
+    va = np.stack(vs).astype(np.int64)                             # [m, nf]
+    return np.einsum("afk,bfk->abk", Ya, np.conj(Ya)), va @ va.T
+
+
 def correlate(job, *, subbands: Optional[Iterable[int]] = None,
               inputs: Optional[Iterable[int]] = None,
               frames: Optional[np.ndarray] = None, chunk: int = 256,
-              rotate: bool = True, frac: bool = True, full_band: bool = False):
+              rotate: bool = True, frac: bool = True, full_band: bool = False,
+              threads: int = 1):
     """O9-O10: (V complex128 [n_sb, M(M+1)/2, K], W int64 [n_sb, M(M+1)/2]).
 
     Inputs are ordered i = s*P + p.  V_ij is the mean over frames valid for
     both stations of Y_i conj(Y_j) (unnormalised FFT); W_ij counts those
     frames; W = 0 gives V = 0.  Entries not requested (subbands/inputs
     subsets) are NaN in V and -1 in W.  `frames` defaults to 0..n_frames-1.
+    `threads` > 1 evaluates frame chunks concurrently; partial sums are still
+    added in chunk order.
     """
-    M, P = job.M, job.n_pols
+    M = job.M
+    P = job.n_pols
     K = job.N if full_band else job.n_chan
     nbl = M * (M + 1) // 2
     sbs = list(range(job.n_subbands)) if subbands is None else list(subbands)
@@ -222,21 +241,21 @@ def correlate(job, *, subbands: Optional[Iterable[int]] = None,
     V = np.full((job.n_subbands, nbl, K), np.nan + 1j * np.nan, dtype=np.complex128)
     W = np.full((job.n_subbands, nbl), -1, dtype=np.int64)
     words = {s: as_words(job.stations[s].frames) for s in sorted({i // P for i in ins})}
+    chunks = [fr[a:a + chunk] for a in range(0, fr.shape[0], chunk)]
     for sb in sbs:
+        def work(fc, sb=sb):
+            return _partial_sums(job, sb, ins, fc, words, rotate, frac, full_band)
+        if threads > 1:
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(threads) as ex:
+                parts = list(ex.map(work, chunks))
+        else:
+            parts = [work(fc) for fc in chunks]
         Vs = np.zeros((len(ins), len(ins), K), dtype=np.complex128)
         Ws = np.zeros((len(ins), len(ins)), dtype=np.int64)
-        for a in range(0, fr.shape[0], chunk):
-            fc = fr[a:a + chunk]
-            Ys, vs = [], []
-            for i in ins:
-                Y, v = station_spectra(job, i // P, sb, i % P, fc, rotate=rotate, frac=frac,
-                                       full_band=full_band, words=words[i // P])
-                Ys.append(Y)
-                vs.append(v)
-            Ya = np.stack(Ys)                                              # [m, nf, K]
-            va = np.stack(vs).astype(np.int64)                             # [m, nf]
-            Vs += np.einsum("afk,bfk->abk", Ya, np.conj(Ya))                # O9
-            Ws += va @ va.T
+        for v, w in parts:                                         # fixed chunk order
+            Vs += v
+            Ws += w
         for ai, i in enumerate(ins):
             for bi, j in enumerate(ins):
                 if i > j:

@@ -1,0 +1,119 @@
+// Small kernels: recording ingest (A0), delay/phase model per frame (A1),
+// accumulator clearing, finalise (A8) and the unpack test tap.
+#include "xc_launch.h"
+
+namespace xc {
+
+__global__ void k_ingest(const uint32_t* __restrict__ words, int64_t n_frames,
+                         uint8_t* __restrict__ ok) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < n_frames) ok[f] = words[f * kFrameWords] == kSync ? 1 : 0;
+}
+
+hipError_t launch_ingest(const uint32_t* words, int64_t n_frames, uint8_t* frame_ok,
+                         hipStream_t s) {
+  if (n_frames <= 0) return hipSuccess;
+  const int b = 256;
+  const int64_t g = (n_frames + b - 1) / b;
+  hipLaunchKernelGGL(k_ingest, dim3((unsigned)g), dim3(b), 0, s, words, n_frames, frame_ok);
+  return hipGetLastError();
+}
+
+__global__ void k_zero(double* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// One thread per (station, block frame).  Writes the integer/fractional delay
+// and validity, and the fringe phase terms of every subband.
+__global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
+                         DelayRec* __restrict__ drec, PhaseRec* __restrict__ prec) {
+  const int fl = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (fl >= nf) return;
+  const DevJob& J = *job;
+  const DevStation& S = J.st[s];
+  const int64_t f = f0 + fl;
+  DelayRec r;
+  frame_delay(S, J, f, &r.n_int, &r.d);
+  r.base = J.sub_start + f * (int64_t)J.N + r.n_int - S.first_sample;
+  const int64_t n_samples = S.n_frames_m5b * (int64_t)J.spf;
+  bool ok = r.base >= 0 && r.base + J.N <= n_samples;
+  if (ok) {
+    const int64_t a = r.base / J.spf, b = (r.base + J.N - 1) / J.spf;
+    for (int64_t m = a; m <= b; ++m) ok = ok && S.frame_ok[m] != 0;
+  }
+  r.valid = ok ? 1 : 0;
+  r.pad = 0;
+  drec[(size_t)s * nf + fl] = r;
+  const int64_t num = J.sub_start + f * (int64_t)J.N + (int64_t)(J.N / 2);
+  const double t = (double)num / J.fs;
+  for (int sb = 0; sb < J.n_subbands; ++sb)
+    prec[((size_t)s * J.n_subbands + sb) * nf + fl] = frame_phase(S, J, sb, t);
+}
+
+hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
+                         DelayRec* drec, PhaseRec* prec, hipStream_t s) {
+  (void)n_subbands;
+  const int b = 64;
+  dim3 grid((nf + b - 1) / b, n_stations);
+  hipLaunchKernelGGL(k_delays, grid, dim3(b), 0, s, job, f0, nf, drec, prec);
+  return hipGetLastError();
+}
+
+__global__ void k_finalise(const double2* __restrict__ vacc, const double* __restrict__ wacc,
+                           float2* __restrict__ vis, float* __restrict__ weight, int nbl,
+                           int n_chan, size_t total) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const size_t row = i / n_chan;          // sb * nbl + bl
+  const int k = (int)(i - row * n_chan);
+  const double w = wacc[row];
+  const double2 a = vacc[i];
+  vis[i] = w > 0.0 ? make_float2((float)(a.x / w), (float)(a.y / w)) : make_float2(0.f, 0.f);
+  if (k == 0) weight[row] = (float)w;
+}
+
+hipError_t launch_finalise(const double2* vacc, const double* wacc, float2* vis, float* weight,
+                           int n_subbands, int nbl, int n_chan, hipStream_t s) {
+  const size_t total = (size_t)n_subbands * nbl * n_chan;
+  const size_t g = (total + 255) / 256;
+  hipLaunchKernelGGL(k_finalise, dim3((unsigned)g), dim3(256), 0, s, vacc, wacc, vis, weight,
+                     nbl, n_chan, total);
+  return hipGetLastError();
+}
+
+// Unpack tap: the same addressing the F stage uses, one thread per sample.
+__global__ void k_debug_unpack(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
+                               int nf, int station, int input, int fl, float* __restrict__ out) {
+  const DevJob& J = *job;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= J.N) return;
+  const DelayRec r = drec[(size_t)station * nf + fl];
+  if (!r.valid) {
+    out[n] = 0.f;
+    return;
+  }
+  const FrameCursor c = make_cursor(J, r.base);
+  int sh0;
+  const uint32_t w = *sample_word(J, J.st[station].words, c, n, sh0);
+  out[n] = level_of((w >> (sh0 + 2 * J.stream_map[input])) & 3u);
+}
+
+hipError_t launch_debug_unpack(const DevJob* job, const DelayRec* drec, int nf, int station,
+                               int input, int fl, float* out, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_debug_unpack, dim3((N + 255) / 256), dim3(256), 0, s, job, drec, nf,
+                     station, input, fl, out);
+  return hipGetLastError();
+}
+
+}  // namespace xc

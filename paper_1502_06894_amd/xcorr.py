@@ -1,0 +1,264 @@
+"""ctypes binding of libxcorr.so (include/xcorr.h): argument marshalling only.
+
+Every step of the correlation runs in the library's HIP kernels.  torch is
+used for device memory and the current stream; there is no fallback: if the
+library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxcorr.so")
+
+XC_OK, XC_E_INVAL, XC_E_RANGE, XC_E_NOMEM, XC_E_HIP, XC_E_CANCELLED, XC_E_TIMEOUT = (
+    0, -1, -2, -3, -4, -5, -6)
+XC_FP32, XC_FP16_MFMA, XC_FP8_MFMA = 0, 1, 2
+KERNEL_KINDS = ["ingest", "delays", "fstage", "xmac", "xmfma", "finalise", "zero"]
+PRECISIONS = {"fp32": XC_FP32, "fp16": XC_FP16_MFMA, "fp8": XC_FP8_MFMA}
+
+
+class XcSetup(C.Structure):
+    _fields_ = [("n_stations", C.c_int32), ("n_subbands", C.c_int32), ("n_pols", C.c_int32),
+                ("n_chan", C.c_int32), ("n_streams_recorded", C.c_int32),
+                ("stream_map", C.POINTER(C.c_int32)), ("fs_hz", C.c_double),
+                ("lo_hz", C.POINTER(C.c_double)), ("sub_start", C.c_int64),
+                ("n_frames", C.c_int64), ("precision", C.c_int32),
+                ("frames_per_block", C.c_int32)]
+
+
+class XcStation(C.Structure):
+    _fields_ = [("frames", C.c_void_p), ("n_frames_m5b", C.c_int64),
+                ("first_sample", C.c_int64), ("frame_ok", C.c_void_p),
+                ("poly_deg", C.c_int32), ("delay_poly", C.POINTER(C.c_double)),
+                ("phase_poly", C.POINTER(C.c_double)), ("poly_t0", C.c_double),
+                ("poly_t1", C.c_double)]
+
+
+class XcOutput(C.Structure):
+    _fields_ = [("vis", C.c_void_p), ("weight", C.c_void_p)]
+
+
+class XcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"xcorr error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library() -> C.CDLL:
+    """Load libxcorr.so from the package directory (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is not built (run __graft_entry__.build())")
+        lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        sig = {
+            "xc_create": (C.c_int, [C.POINTER(P), C.c_int]),
+            "xc_destroy": (None, [P]),
+            "xc_strerror": (C.c_char_p, [C.c_int]),
+            "xc_last_error": (C.c_char_p, [P]),
+            "xc_ingest": (C.c_int, [P, P, C.c_int64, P, P]),
+            "xc_validate": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation)]),
+            "xc_workspace_bytes": (C.c_size_t, [P, C.POINTER(XcSetup), C.POINTER(XcStation)]),
+            "xc_correlate_subint": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
+                                              C.POINTER(XcOutput), P, C.c_size_t, P]),
+            "xc_debug_delays": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation), P, P, P, P,
+                                          P, C.c_size_t, P]),
+            "xc_debug_unpack": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation), C.c_int32,
+                                          C.c_int32, C.c_int64, P, P, C.c_size_t, P]),
+            "xc_debug_spectra": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
+                                           C.c_int64, C.c_int32, P, P, C.c_size_t, P]),
+            "xc_profile_begin": (C.c_int, [P, C.c_int32]),
+            "xc_profile_end": (C.c_int, [P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load_library().xc_strerror(code).decode()
+
+
+class _Marshal:
+    """ctypes views of a Job (keeps the host arrays alive for the call)."""
+
+    def __init__(self, job, precision: int = XC_FP32, frames_per_block: int = 0,
+                 frame_ok: Optional[Sequence] = None):
+        self.keep = []
+        sm = np.ascontiguousarray(job.stream_map, dtype=np.int32)
+        lo = np.ascontiguousarray(job.lo_hz, dtype=np.float64)
+        self.keep += [sm, lo]
+        self.setup = XcSetup(job.n_stations, job.n_subbands, job.n_pols, job.n_chan,
+                             job.n_streams, sm.ctypes.data_as(C.POINTER(C.c_int32)),
+                             float(job.fs_hz), lo.ctypes.data_as(C.POINTER(C.c_double)),
+                             int(job.sub_start), int(job.n_frames), int(precision),
+                             int(frames_per_block))
+        arr = (XcStation * job.n_stations)()
+        for i, st in enumerate(job.stations):
+            fr = st.frames
+            if not (isinstance(fr, torch.Tensor) and fr.is_cuda and fr.dtype == torch.int32
+                    and fr.is_contiguous() and fr.dim() == 2 and fr.shape[1] == 2504):
+                raise ValueError(f"station {i}: frames must be a contiguous cuda int32 [n, 2504]")
+            dp = np.ascontiguousarray(st.delay_poly, dtype=np.float64)
+            self.keep.append(dp)
+            pp_ptr = None
+            if st.phase_poly is not None:
+                pp = np.ascontiguousarray(st.phase_poly, dtype=np.float64)
+                assert pp.shape == (job.n_subbands, dp.shape[0]), pp.shape
+                self.keep.append(pp)
+                pp_ptr = pp.ctypes.data_as(C.POINTER(C.c_double))
+            ok = None
+            if frame_ok is not None and frame_ok[i] is not None:
+                ok = frame_ok[i].data_ptr()
+            arr[i] = XcStation(fr.data_ptr(), fr.shape[0], int(st.first_sample), ok,
+                               dp.shape[0] - 1, dp.ctypes.data_as(C.POINTER(C.c_double)),
+                               pp_ptr, float(st.poly_span[0]), float(st.poly_span[1]))
+        self.stations = arr
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Correlator:
+    """One library context on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        self.ctx = C.c_void_p()
+        rc = self.lib.xc_create(C.byref(self.ctx), device)
+        if rc != XC_OK:
+            raise XcError(rc, strerror(rc))
+
+    def close(self):
+        if self.ctx:
+            self.lib.xc_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != XC_OK:
+            raise XcError(rc, f"{strerror(rc)}: {self.lib.xc_last_error(self.ctx).decode()}")
+
+    # ------------------------------------------------------------------ sizes
+    def workspace_bytes(self, job, precision: int = XC_FP32, frames_per_block: int = 0,
+                        frame_ok=None) -> int:
+        m = _Marshal(job, precision, frames_per_block, frame_ok)
+        self._check(self.lib.xc_validate(self.ctx, C.byref(m.setup), m.stations))
+        return int(self.lib.xc_workspace_bytes(self.ctx, C.byref(m.setup), m.stations))
+
+    def alloc_workspace(self, job, **kw) -> torch.Tensor:
+        n = self.workspace_bytes(job, **kw)
+        if n == 0:
+            raise XcError(XC_E_INVAL, "invalid job (workspace size 0)")
+        return torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def alloc_output(self, job):
+        dev = f"cuda:{self.device}"
+        vis = torch.empty(job.n_subbands, job.n_baselines, job.n_chan, dtype=torch.complex64,
+                          device=dev)
+        w = torch.empty(job.n_subbands, job.n_baselines, dtype=torch.float32, device=dev)
+        return vis, w
+
+    # ------------------------------------------------------------------ calls
+    def ingest(self, frames: torch.Tensor, frame_ok: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+        if frame_ok is None:
+            frame_ok = torch.empty(frames.shape[0], dtype=torch.uint8, device=frames.device)
+        self._check(self.lib.xc_ingest(self.ctx, frames.data_ptr(), frames.shape[0],
+                                       frame_ok.data_ptr(), _stream_ptr(stream)))
+        return frame_ok
+
+    def correlate(self, job, *, precision: int = XC_FP32, frames_per_block: int = 0,
+                  out=None, workspace: Optional[torch.Tensor] = None, stream=None,
+                  frame_ok=None):
+        """Returns (vis complex64 [n_sb, nbl, n_chan], weight float32 [n_sb, nbl])."""
+        m = _Marshal(job, precision, frames_per_block, frame_ok)
+        if workspace is None:
+            workspace = self.alloc_workspace(job, precision=precision,
+                                             frames_per_block=frames_per_block, frame_ok=frame_ok)
+        vis, w = out if out is not None else self.alloc_output(job)
+        o = XcOutput(vis.data_ptr(), w.data_ptr())
+        self._check(self.lib.xc_correlate_subint(self.ctx, C.byref(m.setup), m.stations,
+                                                 C.byref(o), workspace.data_ptr(),
+                                                 workspace.numel(), _stream_ptr(stream)))
+        return vis, w
+
+    def profile_begin(self, max_launches: int = 8192):
+        """Time every kernel launch of this context with HIP events on its stream."""
+        self._check(self.lib.xc_profile_begin(self.ctx, max_launches))
+
+    def profile_end(self) -> dict:
+        """{kind: (total ms, launches)} since profile_begin (synchronises)."""
+        ms = np.zeros(len(KERNEL_KINDS), np.float64)
+        n = np.zeros(len(KERNEL_KINDS), np.int64)
+        self._check(self.lib.xc_profile_end(self.ctx, ms.ctypes.data, n.ctypes.data))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def debug_delays(self, job, workspace: Optional[torch.Tensor] = None, frames_per_block=0):
+        m = _Marshal(job, XC_FP32, frames_per_block)
+        if workspace is None:
+            workspace = self.alloc_workspace(job, frames_per_block=frames_per_block)
+        S, F, nsb = job.n_stations, job.n_frames, job.n_subbands
+        n_int = np.zeros((S, F), np.int64)
+        d = np.zeros((S, F), np.float64)
+        valid = np.zeros((S, F), np.int32)
+        phi0 = np.zeros((S, nsb, F), np.float64)
+        self._check(self.lib.xc_debug_delays(
+            self.ctx, C.byref(m.setup), m.stations, n_int.ctypes.data, d.ctypes.data,
+            valid.ctypes.data, phi0.ctypes.data, workspace.data_ptr(), workspace.numel(),
+            _stream_ptr(None)))
+        return dict(n_int=n_int, d=d, valid=valid.astype(bool), phi0=phi0)
+
+    def debug_unpack(self, job, station: int, inp: int, frame: int,
+                     workspace: Optional[torch.Tensor] = None) -> np.ndarray:
+        m = _Marshal(job)
+        if workspace is None:
+            workspace = self.alloc_workspace(job)
+        out = np.zeros(job.N, np.float32)
+        self._check(self.lib.xc_debug_unpack(self.ctx, C.byref(m.setup), m.stations, station,
+                                             inp, frame, out.ctypes.data, workspace.data_ptr(),
+                                             workspace.numel(), _stream_ptr(None)))
+        return out
+
+    def debug_spectra(self, job, frame0: int, n: int, frames_per_block: int = 0,
+                      workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Spectra after the F stage: complex64 [n_sb, n, M, n_chan]."""
+        m = _Marshal(job, XC_FP32, frames_per_block)
+        if workspace is None:
+            workspace = self.alloc_workspace(job, frames_per_block=frames_per_block)
+        spec = torch.empty(job.n_subbands, n, job.M, job.n_chan, dtype=torch.complex64,
+                           device=f"cuda:{self.device}")
+        self._check(self.lib.xc_debug_spectra(self.ctx, C.byref(m.setup), m.stations, frame0, n,
+                                              spec.data_ptr(), workspace.data_ptr(),
+                                              workspace.numel(), _stream_ptr(None)))
+        return spec
+
+
+def job_to_device(job, device="cuda:0"):
+    """Copy a job's recordings to the GPU (in place; returns the job)."""
+    for st in job.stations:
+        if not isinstance(st.frames, torch.Tensor):
+            st.frames = torch.from_numpy(np.ascontiguousarray(st.frames).view(np.int32))
+        st.frames = st.frames.to(device).contiguous()
+    return job

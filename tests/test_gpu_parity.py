@@ -1,0 +1,186 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: bit-exact for the integer delay, fractional delay, validity and 2-bit
+unpack; relative L2 error over channels <= 1e-5 per baseline and subband for
+visibilities (autos included); fringe phase at frame centres within 1e-8 turns.
+"""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fx
+from synth import configs
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def xc():
+    from paper_1502_06894_amd import xcorr
+    return xcorr
+
+
+@pytest.fixture(scope="module")
+def corr(xc):
+    return xc.Correlator(0)
+
+
+def _on_gpu(xc, job):
+    return xc.job_to_device(job)
+
+
+def _oracle_delays(job):
+    F = np.arange(job.n_frames)
+    out = []
+    for st in job.stations:
+        w = fx.as_words(st.frames)
+        n_int, d = fx.frame_delays(st.delay_poly, job.sub_start, job.N, job.fs_hz, F)
+        base, valid = fx.frame_valid(w, job.n_streams, st.first_sample, job.sub_start, job.N, F,
+                                     n_int)
+        out.append((n_int, d, valid))
+    return out
+
+
+def _jobs_for_delays():
+    return [
+        configs.small_job(n_stations=3, n_subbands=2, n_pols=2, n_chan=128, C=4, n_frames=300),
+        configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=8192, C=1, n_frames=40,
+                          seed=3),
+        configs.c2_job(n_frames=700, n_subbands=2, n_stations=4),
+    ]
+
+
+@pytest.mark.parametrize("ji", range(3))
+def test_delays_bit_exact(xc, corr, ji):
+    job = _jobs_for_delays()[ji]
+    ref = _oracle_delays(job)
+    _on_gpu(xc, job)
+    got = corr.debug_delays(job, frames_per_block=64)
+    for s, (n_int, d, valid) in enumerate(ref):
+        assert np.array_equal(got["n_int"][s], n_int), s
+        assert np.array_equal(got["d"][s], d), s                      # bit-exact doubles
+        assert np.array_equal(got["valid"][s], valid), s
+        for sb in range(job.n_subbands):
+            st = job.stations[s]
+            pp = None if st.phase_poly is None else st.phase_poly[sb]
+            f = np.arange(job.n_frames)
+            ph = fx.fringe_phase(st.delay_poly, pp, job.lo_hz[sb], job.sub_start, job.N,
+                                 job.fs_hz, f)[:, job.N // 2]
+            err = (got["phi0"][s, sb] - ph + 0.5) % 1.0 - 0.5
+            assert np.max(np.abs(err)) < 1e-8, (s, sb)
+
+
+def test_unpack_bit_exact(xc, corr):
+    rng = np.random.default_rng(1)
+    for C, P, nsb in [(1, 1, 1), (2, 1, 2), (4, 2, 2), (8, 2, 4), (16, 2, 8)]:
+        job = configs.small_job(n_stations=2, n_subbands=nsb, n_pols=P, n_chan=1024, C=C,
+                                n_frames=60, seed=C)
+        words = [fx.as_words(st.frames) for st in job.stations]
+        _on_gpu(xc, job)
+        for _ in range(6):
+            s = int(rng.integers(0, 2))
+            inp = int(rng.integers(0, nsb * P))
+            f = int(rng.integers(0, job.n_frames))
+            got = corr.debug_unpack(job, s, inp, f)
+            y, _, valid = fx.rotated_samples(job, s, inp // P, inp % P, np.array([f]),
+                                             rotate=False, words=words[s])
+            want = y[0].real.astype(np.float32) if valid[0] else np.zeros(job.N, np.float32)
+            assert np.array_equal(got, want), (C, s, inp, f)
+
+
+@pytest.mark.parametrize("n_chan,C", [(128, 1), (256, 2), (1024, 16), (4096, 4), (8192, 8)])
+def test_spectra_parity(xc, corr, n_chan, C):
+    P, nsb = (2, 2) if C >= 4 else (1, 1)
+    job = configs.small_job(n_stations=2, n_subbands=nsb, n_pols=P, n_chan=n_chan, C=C,
+                            n_frames=12, seed=n_chan)
+    refs = {}
+    for s in range(2):
+        for sb in range(nsb):
+            for p in range(P):
+                refs[(s, sb, p)] = fx.station_spectra(job, s, sb, p, np.arange(12))[0]
+    _on_gpu(xc, job)
+    spec = corr.debug_spectra(job, 0, 12).cpu().numpy()          # [nsb, n, M, n_chan]
+    for (s, sb, p), Y in refs.items():
+        got = spec[sb, :, s * P + p, :]
+        assert rel_l2(got, Y) < 3e-6, (s, sb, p)
+
+
+VIS_CASES = [
+    # name, small_job kwargs, frames_per_block
+    ("c1like", dict(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=300), 0),
+    ("ragged", dict(n_stations=3, n_subbands=2, n_pols=2, n_chan=128, C=4, n_frames=37), 16),
+    ("c2like", dict(n_stations=4, n_subbands=8, n_pols=2, n_chan=1024, C=16, n_frames=40), 0),
+    ("c4like", dict(n_stations=5, n_subbands=4, n_pols=1, n_chan=4096, C=4, n_frames=12), 0),
+    ("big_n", dict(n_stations=2, n_subbands=1, n_pols=1, n_chan=8192, C=2, n_frames=6), 0),
+    ("matched", dict(n_stations=6, n_subbands=2, n_pols=1, n_chan=512, C=8, n_frames=50,
+                     realistic=False), 0),
+    ("one_frame", dict(n_stations=2, n_subbands=1, n_pols=2, n_chan=2048, C=2, n_frames=1), 0),
+    ("m_not_mult4", dict(n_stations=7, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=20), 8),
+]
+
+
+@pytest.mark.parametrize("name,kw,fpb", VIS_CASES, ids=[c[0] for c in VIS_CASES])
+def test_visibility_parity(xc, corr, name, kw, fpb):
+    job = configs.small_job(**kw, seed=zlib.crc32(name.encode()) % 1000)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    vis, w = corr.correlate(job, frames_per_block=fpb)
+    torch.cuda.synchronize()
+    vis, w = vis.cpu().numpy(), w.cpu().numpy()
+    assert np.array_equal(w, W.astype(np.float32))
+    assert rel_l2(vis, V) < TOL, name
+
+
+def test_bad_frames_and_out_of_buffer(xc, corr):
+    job = configs.small_job(n_stations=3, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=400,
+                            realistic=False, seed=5)
+    st = job.stations[1]
+    st.frames = st.frames.clone()
+    st.frames[2, 0] = 0                                # bad sync in recording frame 2
+    job.stations[2].frames = job.stations[2].frames[:-1].contiguous()   # last frames out of buffer
+    V, W = fx.correlate(job, threads=8)
+    assert W.min() < job.n_frames
+    _on_gpu(xc, job)
+    vis, w = corr.correlate(job)
+    assert np.array_equal(w.cpu().numpy(), W.astype(np.float32))
+    assert rel_l2(vis.cpu().numpy(), V) < TOL
+
+
+def test_ingest_mask_and_supplied_mask(xc, corr):
+    job = configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=200,
+                            realistic=False, seed=8)
+    job.stations[0].frames = job.stations[0].frames.clone()
+    job.stations[0].frames[1, 0] = 123
+    want = fx.sync_ok(fx.as_words(job.stations[0].frames))
+    _on_gpu(xc, job)
+    ok = corr.ingest(job.stations[0].frames)
+    assert np.array_equal(ok.cpu().numpy().astype(bool), want)
+    oks = [corr.ingest(st.frames) for st in job.stations]
+    v1, w1 = corr.correlate(job)
+    v2, w2 = corr.correlate(job, frame_ok=oks)
+    assert torch.equal(v1, v2) and torch.equal(w1, w2)
+
+
+def test_error_codes(xc, corr):
+    job = configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=10)
+    _on_gpu(xc, job)
+    with pytest.raises(xc.XcError) as e:
+        corr.correlate(job, workspace=torch.empty(1024, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == xc.XC_E_NOMEM
+    job.stations[0].poly_span = (0.0, 10.0)
+    with pytest.raises(xc.XcError) as e:
+        corr.correlate(job)
+    assert e.value.code == xc.XC_E_RANGE
+
+
+def test_deterministic_repeat(xc, corr):
+    job = configs.small_job(n_stations=4, n_subbands=2, n_pols=2, n_chan=512, C=4, n_frames=90)
+    _on_gpu(xc, job)
+    a = corr.correlate(job)[0].clone()
+    for _ in range(3):
+        assert torch.equal(corr.correlate(job)[0], a)
