@@ -1,0 +1,236 @@
+"""Throughput benchmark of the FX correlation path on one MI355X.
+
+One step = one whole sub-integration through the C ABI (A0 ingest .. A8
+finalise) on inputs already resident in HBM.  Default workload: 10 stations
+(1 space + 9 ground), 8 x 16 MHz subbands, dual pol (16 recorded streams),
+1024 channels, 4 s = 62 500 FFT frames of 2048 samples per input.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+
+  python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu-baseline]
+  python bench.py --calibrate-copy     # plain device copy of known size, for counter scaling
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published
+
+
+def log(msg: str):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1502_06894_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+F_SOURCES = ["k_fstage.hip", "xc_fft.h", "xc_dev.h"]
+X_SOURCES = ["k_xmac.hip", "xc_dev.h"]
+
+
+def make_job(name: str):
+    from synth import configs
+    if name == "c2":
+        return configs.c2_job(device="cuda", realistic=True), (
+            "C2: 10 stations (1 space + 9 ground), 8 x 16 MHz subbands, dual pol, "
+            "1024 channels, 4 s sub-int, 2-bit")
+    if name == "c1":
+        return configs.c1_job(), ("C1: 2 stations (space + ground), 1 x 16 MHz, single pol, "
+                                  "256 channels, 0.5 s, 2-bit, exact-physics generator")
+    if name == "c4":
+        return configs.c4_job(device="cuda"), (
+            "C4: 32 stations, 4 x 32 MHz subbands, single pol, 4096 channels, 1 s, 2-bit")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profile(kind: str, src_hash: str, launches_units: float):
+    """HBM bytes per launch from committed counter summaries, if they match the kernel."""
+    path = os.path.join(ROOT, "profiles", "hbm_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    e = d.get(kind)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(job, budget_s: float = 12.0, max_frames: int = 8192):
+    """The FP64 oracle on a bounded sample of the same workload (subband 0, all inputs)."""
+    import torch
+    from oracle import fx
+    from synth.job import Job, Station
+
+    cores = min(16, os.cpu_count() or 1)
+    spf = 40000 // job.n_streams
+    stations = []
+    for st in job.stations:
+        n_int, _ = fx.frame_delays(st.delay_poly, job.sub_start, job.N, job.fs_hz,
+                                   np.array([0, max_frames - 1]))
+        base = job.sub_start + np.array([0, max_frames - 1]) * job.N + n_int - st.first_sample
+        lo = max(0, int(base.min()) // spf - 1)
+        hi = min(st.n_frames_m5b, (int(base.max()) + job.N) // spf + 2)
+        stations.append(Station(frames=st.frames[lo:hi].cpu(), first_sample=st.first_sample + lo * spf,
+                                delay_poly=st.delay_poly, phase_poly=st.phase_poly,
+                                poly_span=st.poly_span, station_id=st.station_id))
+    sub = Job(n_stations=job.n_stations, n_subbands=job.n_subbands, n_pols=job.n_pols,
+              n_chan=job.n_chan, n_streams=job.n_streams, stream_map=job.stream_map,
+              fs_hz=job.fs_hz, lo_hz=job.lo_hz, sub_start=job.sub_start, n_frames=max_frames,
+              stations=stations)
+    chunk = 64 * cores            # one call spreads 64-frame chunks over all threads
+    done = 0
+    t0 = time.perf_counter()
+    while done < max_frames and time.perf_counter() - t0 < budget_s:
+        n = min(chunk, max_frames - done)
+        fx.correlate(sub, subbands=[0], frames=np.arange(done, done + n), threads=cores, chunk=64)
+        done += n
+    dt = time.perf_counter() - t0
+    ss = job.M * done * job.N
+    return {"value": ss / dt / 1e9, "unit": "G station-samples/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"subband 0 of {job.n_subbands}, all {job.M} inputs, frames 0..{done - 1} "
+                      f"of {job.n_frames} ({ss:.3e} station-samples in {dt:.1f} s, "
+                      f"{cores} threads)"}
+
+
+def calibrate_copy():
+    import torch
+    n = 1 << 30
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "dispatches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--frames-per-block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: the correlation path is built and measured on a "
+              "single MI355X (multi-GPU sharding by subband x time is design-only).",
+              file=sys.stderr)
+        sys.exit(2)
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import torch
+    from paper_1502_06894_amd import xcorr
+
+    log(f"generating workload {a.workload} on the GPU")
+    t = time.perf_counter()
+    job, desc = make_job(a.workload)
+    xcorr.job_to_device(job, "cuda:0")
+    torch.cuda.synchronize()
+    log(f"workload ready in {time.perf_counter() - t:.1f} s: {job.station_samples:.3e} "
+        f"station-samples per step")
+    corr = xcorr.Correlator(0)
+    oks = [corr.ingest(st.frames) for st in job.stations]
+    ws = corr.alloc_workspace(job, frames_per_block=a.frames_per_block, frame_ok=oks)
+    out = corr.alloc_output(job)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        corr.correlate(job, frames_per_block=a.frames_per_block, out=out, workspace=ws,
+                       frame_ok=oks, stream=stream)
+
+    for i in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({a.warmup} steps)")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
+    T = a.frames_per_block or min(1024, job.n_frames)
+    blocks = -(-job.n_frames // T)
+    corr.profile_begin(max_launches=a.steps * (3 * blocks + 4) + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = corr.profile_end()
+    step_ms = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    dt = t1 - t0
+    ss = job.station_samples
+    value = ss * a.steps / dt / 1e9
+    log(f"timed {a.steps} steps: {dt * 1e3 / a.steps:.2f} ms/step, {value:.1f} G ss/s")
+    for k, (ms, n) in prof.items():
+        if n:
+            log(f"  kernel {k:9s}: {ms / a.steps:8.3f} ms/step over {n // a.steps} launches")
+
+    # roofline of the dominant kernel (algorithmic bytes per station-sample)
+    per_ss = {"fstage": (4.25, F_SOURCES), "xmac": (4.0, X_SOURCES)}
+    dom = max(per_ss, key=lambda k: prof[k][0])
+    bytes_per_ss, srcs = per_ss[dom]
+    ms_tot, n_launch = prof[dom]
+    alg_bytes = bytes_per_ss * ss * a.steps
+    achieved = alg_bytes / (ms_tot * 1e-3) / 1e9
+    src_hash = kernel_source_hash(srcs)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profile(dom, src_hash, 0), "kernel": dom,
+            "kernel_ms_per_launch": round(ms_tot / n_launch, 4),
+            "algorithmic_bytes_per_launch": round(alg_bytes / n_launch),
+            "bytes_per_station_sample": bytes_per_ss, "source_hash": src_hash}
+    kernels = {k: {"ms_per_step": round(ms / a.steps, 3), "launches_per_step": n // a.steps}
+               for k, (ms, n) in prof.items() if n}
+
+    res = {
+        "metric": "correlated station-samples/s",
+        "value": round(value, 2),
+        "unit": "G station-samples/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(dt * 1e3 / a.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": desc, "stations": job.n_stations, "subbands": job.n_subbands,
+                   "pols": job.n_pols, "channels": job.n_chan, "fft_len": job.N,
+                   "frames": job.n_frames, "station_samples_per_step": ss,
+                   "frames_per_block": a.frames_per_block or min(1024, job.n_frames),
+                   "precision": "fp32", "parallelism": "single GPU"},
+        "roofline": roof,
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
+                       "p99": round(float(np.percentile(step_ms, 99)), 3)},
+        "kernels": kernels,
+        "cpu_baseline": None,
+    }
+    if not a.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(job)
+        log(f"oracle: {res['cpu_baseline']['value'] * 1e3:.2f} M ss/s "
+            f"({res['cpu_baseline']['sample']})")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -97,7 +97,8 @@ typedef struct {
   int64_t sub_start;           /* reference-time sample index of the sub-integration start */
   int64_t n_frames;            /* FFT frames in the sub-integration (>= 1) */
   int32_t precision;           /* XC_FP32 | XC_FP16_MFMA | XC_FP8_MFMA */
-  int32_t frames_per_block;    /* frames staged per F/X round, 0 = library's choice (<= 256) */
+  int32_t frames_per_block;    /* frames staged per F/X round, 0 = library default (1024);
+                                  at most 2048 */
 } xc_setup;
 
 typedef struct {

@@ -70,25 +70,56 @@ hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int6
   return hipGetLastError();
 }
 
-__global__ void k_finalise(const double2* __restrict__ vacc, const double* __restrict__ wacc,
+__global__ void k_weights(const DelayRec* __restrict__ drec, int S, int nf,
+                          double* __restrict__ wst) {
+  const int si = blockIdx.x, sj = threadIdx.x;
+  if (sj < si || sj >= S) return;
+  int cnt = 0;
+  for (int f = 0; f < nf; ++f)
+    cnt += drec[(size_t)si * nf + f].valid & drec[(size_t)sj * nf + f].valid;
+  wst[si * S + sj] += (double)cnt;
+}
+
+hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* wst,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_weights, dim3(n_stations), dim3(64), 0, s, drec, n_stations, nf, wst);
+  return hipGetLastError();
+}
+
+__global__ void k_finalise(const double2* __restrict__ vacc, int n_slots, size_t slot_stride,
+                           const double* __restrict__ wst, int S, int P, int M,
                            float2* __restrict__ vis, float* __restrict__ weight, int nbl,
                            int n_chan, size_t total) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const size_t row = i / n_chan;          // sb * nbl + bl
-  const int k = (int)(i - row * n_chan);
-  const double w = wacc[row];
-  const double2 a = vacc[i];
-  vis[i] = w > 0.0 ? make_float2((float)(a.x / w), (float)(a.y / w)) : make_float2(0.f, 0.f);
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const size_t row = e / n_chan;          // sb * nbl + bl
+  const int k = (int)(e - row * n_chan);
+  const int bl = (int)(row % nbl);
+  int i = 0, rem = bl;                    // bl -> (i, j), row-major upper triangle
+  while (rem >= M - i) {
+    rem -= M - i;
+    ++i;
+  }
+  const int j = i + rem;
+  const double w = wst[(i / P) * S + (j / P)];
+  double2 a = vacc[e];
+  for (int q = 1; q < n_slots; ++q) {     // fixed slot order
+    const double2 b = vacc[e + q * slot_stride];
+    a.x += b.x;
+    a.y += b.y;
+  }
+  vis[e] = w > 0.0 ? make_float2((float)(a.x / w), (float)(a.y / w)) : make_float2(0.f, 0.f);
   if (k == 0) weight[row] = (float)w;
 }
 
-hipError_t launch_finalise(const double2* vacc, const double* wacc, float2* vis, float* weight,
-                           int n_subbands, int nbl, int n_chan, hipStream_t s) {
+hipError_t launch_finalise(const double2* vacc, int n_slots, size_t slot_stride,
+                           const double* wst, int n_stations, int n_pols, float2* vis,
+                           float* weight, int n_subbands, int M, int n_chan, hipStream_t s) {
+  const int nbl = M * (M + 1) / 2;
   const size_t total = (size_t)n_subbands * nbl * n_chan;
   const size_t g = (total + 255) / 256;
-  hipLaunchKernelGGL(k_finalise, dim3((unsigned)g), dim3(256), 0, s, vacc, wacc, vis, weight,
-                     nbl, n_chan, total);
+  hipLaunchKernelGGL(k_finalise, dim3((unsigned)g), dim3(256), 0, s, vacc, n_slots, slot_stride,
+                     wst, n_stations, n_pols, M, vis, weight, nbl, n_chan, total);
   return hipGetLastError();
 }
 

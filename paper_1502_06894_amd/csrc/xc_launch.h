@@ -22,14 +22,23 @@ hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int6
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
                          const PhaseRec* prec, const float2* tw, float2* spec, int nf,
                          hipStream_t s);
-// A6: accumulate the block's spectra into vacc [n_sb][nbl][n_chan] (double2) and
-// weights wacc [n_sb][nbl].
+// Frames one X workgroup accumulates in FP32 before adding to its FP64 slot.
+constexpr int kXmacFramesPerSplit = 256;
+// Accumulator slots a block of nf frames uses (frames split kXmacFramesPerSplit at a time).
+int xmac_splits(int nf);
+// A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
+// (double2), slot_stride elements apart.
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
-                       const DelayRec* drec, const float2* spec, double2* vacc, double* wacc,
-                       int nf, int n_pols, hipStream_t s);
-// A8: vis = vacc / W (W = 0 -> 0), weight = W.
-hipError_t launch_finalise(const double2* vacc, const double* wacc, float2* vis, float* weight,
-                           int n_subbands, int nbl, int n_chan, hipStream_t s);
+                       const float2* spec, double2* vacc, size_t slot_stride, int nf,
+                       hipStream_t s);
+// Frames of the block valid for both stations of each station pair: wst[si][sj] += count.
+hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* wst,
+                          hipStream_t s);
+// A8: vis = (sum of the n_slots slots) / W (W = 0 -> 0), weight = W, with W of
+// baseline (i, j) taken from wst[i / P][j / P].
+hipError_t launch_finalise(const double2* vacc, int n_slots, size_t slot_stride,
+                           const double* wst, int n_stations, int n_pols, float2* vis,
+                           float* weight, int n_subbands, int M, int n_chan, hipStream_t s);
 // Test tap: unpacked levels of one (station, input, block frame).
 hipError_t launch_debug_unpack(const DevJob* job, const DelayRec* drec, int nf, int station,
                                int input, int fl, float* out, int N, hipStream_t s);

@@ -84,12 +84,17 @@ hipError_t timed(xc_ctx* c, int kind, hipStream_t s, Fn&& fn) {
 struct Layout {
   size_t desc = 0, mask = 0, drec = 0, prec = 0, spec = 0, vacc = 0, wacc = 0, total = 0;
   size_t desc_bytes = 0;
+  int n_slots = 1;                // FP64 accumulator slots of the X stage
+  size_t slot_stride = 0;         // double2 elements per slot
   std::vector<size_t> mask_off;   // per station, SIZE_MAX if caller supplies frame_ok
   int T = 0;                      // frames per block
 };
 
+constexpr int kMaxBlockFrames = 2048;
+constexpr int kDefaultBlockFrames = 1024;
+
 int block_frames(const xc_setup* s) {
-  int64_t T = s->frames_per_block > 0 ? s->frames_per_block : 256;
+  int64_t T = s->frames_per_block > 0 ? s->frames_per_block : kDefaultBlockFrames;
   if (T > s->n_frames) T = s->n_frames;
   return (int)T;
 }
@@ -120,8 +125,9 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
   if (s->n_frames < 1) return fail(c, XC_E_INVAL, "n_frames=%lld", (long long)s->n_frames);
   if (s->precision != XC_FP32)
     return fail(c, XC_E_INVAL, "precision %d not available on this path", s->precision);
-  if (s->frames_per_block < 0 || s->frames_per_block > 256)
-    return fail(c, XC_E_INVAL, "frames_per_block=%d outside 0..256", s->frames_per_block);
+  if (s->frames_per_block < 0 || s->frames_per_block > kMaxBlockFrames)
+    return fail(c, XC_E_INVAL, "frames_per_block=%d outside 0..%d", s->frames_per_block,
+                kMaxBlockFrames);
   if (!st) return fail(c, XC_E_INVAL, "stations is NULL");
   const int N = 2 * s->n_chan;
   const double t0 = (double)s->sub_start / s->fs_hz;
@@ -165,10 +171,12 @@ Layout layout_of(const xc_setup* s, const xc_station* st) {
   off += align_up((size_t)S * nsb * L.T * sizeof(PhaseRec));
   L.spec = off;
   off += align_up((size_t)nsb * L.T * M * s->n_chan * sizeof(float2));
+  L.n_slots = xmac_splits(L.T);
+  L.slot_stride = (size_t)nsb * nbl * s->n_chan;
   L.vacc = off;
-  off += (size_t)nsb * nbl * s->n_chan * sizeof(double2);   // wacc follows directly
+  off += (size_t)L.n_slots * L.slot_stride * sizeof(double2);   // wacc follows directly
   L.wacc = off;
-  off += align_up((size_t)nsb * nbl * sizeof(double));
+  off += align_up((size_t)S * S * sizeof(double));
   L.total = off;
   return L;
 }
@@ -364,7 +372,7 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
   double2* vacc = reinterpret_cast<double2*>(ws + L.vacc);
   double* wacc = reinterpret_cast<double*>(ws + L.wacc);
   const int S = s->n_stations, nsb = s->n_subbands, M = S * s->n_pols;
-  const int nbl = M * (M + 1) / 2, N = 2 * s->n_chan;
+  const int N = 2 * s->n_chan;
   hipError_t e = timed(c, XC_K_ZERO, stream, [&] {
     return launch_zero(reinterpret_cast<double*>(vacc), (L.total - L.vacc) / sizeof(double),
                        stream);
@@ -372,20 +380,23 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
   if (e != hipSuccess) return hip_fail(c, e, "zero");
   for (int64_t f0 = 0; f0 < s->n_frames; f0 += L.T) {
     const int nf = (int)((s->n_frames - f0) < L.T ? (s->n_frames - f0) : L.T);
-    e = timed(c, XC_K_DELAYS, stream,
-              [&] { return launch_delays(dj, S, nsb, f0, nf, drec, prec, stream); });
+    e = timed(c, XC_K_DELAYS, stream, [&] {
+      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec, prec, stream);
+      return r == hipSuccess ? launch_weights(drec, S, nf, wacc, stream) : r;
+    });
     if (e != hipSuccess) return hip_fail(c, e, "delays");
     e = timed(c, XC_K_FSTAGE, stream,
               [&] { return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nf, stream); });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
     e = timed(c, XC_K_XMAC, stream, [&] {
-      return launch_xmac(dj, M, s->n_chan, nsb, drec, spec, vacc, wacc, nf, s->n_pols, stream);
+      return launch_xmac(dj, M, s->n_chan, nsb, spec, vacc, L.slot_stride, nf, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "xmac");
   }
   e = timed(c, XC_K_FINALISE, stream, [&] {
-    return launch_finalise(vacc, wacc, static_cast<float2*>(out->vis), out->weight, nsb, nbl,
-                           s->n_chan, stream);
+    return launch_finalise(vacc, L.n_slots, L.slot_stride, wacc, S, s->n_pols,
+                           static_cast<float2*>(out->vis), out->weight, nsb, M, s->n_chan,
+                           stream);
   });
   if (e != hipSuccess) return hip_fail(c, e, "finalise");
   return XC_OK;

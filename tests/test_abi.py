@@ -92,7 +92,7 @@ def test_workspace_bytes_and_validation_on_host():
     s2, st2, keep2 = _setup(frames_per_block=64)
     assert lib.xc_workspace_bytes(None, C.byref(s2), st2) < n
     for bad in [dict(n_chan=300), dict(n_chan=64), dict(n_streams_recorded=3),
-                dict(n_pols=3), dict(n_stations=0), dict(n_frames=0), dict(frames_per_block=300),
+                dict(n_pols=3), dict(n_stations=0), dict(n_frames=0), dict(frames_per_block=3000),
                 dict(precision=7)]:
         sb, stb, kb = _setup(**bad)
         assert lib.xc_workspace_bytes(None, C.byref(sb), stb) == 0, bad

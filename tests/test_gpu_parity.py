@@ -121,6 +121,8 @@ VIS_CASES = [
                      realistic=False), 0),
     ("one_frame", dict(n_stations=2, n_subbands=1, n_pols=2, n_chan=2048, C=2, n_frames=1), 0),
     ("m_not_mult4", dict(n_stations=7, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=20), 8),
+    ("splits", dict(n_stations=3, n_subbands=1, n_pols=2, n_chan=128, C=2, n_frames=700), 600),
+    ("m32", dict(n_stations=32, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=30), 0),
 ]
 
 
