@@ -9,6 +9,7 @@ Prints one JSON line (stdout).  Progress goes to stderr.
 
   python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu-baseline]
   python bench.py --calibrate-copy     # plain device copy of known size, for counter scaling
+  python bench.py --rocpd-summary DB   # per-kernel table from a rocprofv3 database
 """
 from __future__ import annotations
 
@@ -44,10 +45,11 @@ F_SOURCES = ["k_fstage.hip", "xc_fft.h", "xc_dev.h"]
 X_SOURCES = ["k_xmac.hip", "xc_dev.h"]
 
 
-def make_job(name: str):
+def make_job(name: str, frames: int = 0):
     from synth import configs
     if name == "c2":
-        return configs.c2_job(device="cuda", realistic=True), (
+        kw = {"n_frames": frames} if frames else {}
+        return configs.c2_job(device="cuda", realistic=True, **kw), (
             "C2: 10 stations (1 space + 9 ground), 8 x 16 MHz subbands, dual pol, "
             "1024 channels, 4 s sub-int, 2-bit")
     if name == "c1":
@@ -110,6 +112,62 @@ def cpu_baseline(job, budget_s: float = 12.0, max_frames: int = 8192):
                       f"{cores} threads)"}
 
 
+def short_kernel_name(name: str) -> str:
+    """'void xc::k_fstage<2048>(...)' -> 'xc::k_fstage<2048>'; other names cut to 60 chars."""
+    n = name.replace("void ", "", 1)
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    return n[:60]
+
+
+def rocpd_summary(db_path: str) -> str:
+    """Per-kernel dispatch statistics (and counter means) from a rocprofv3 rocpd database."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    cur = db.cursor()
+    lines = []
+    rows = cur.execute("select name, duration, lds_size, scratch_size, vgpr_count, "
+                       "accum_vgpr_count, grid_x, grid_y, grid_z, workgroup_x from kernels")
+    stats = {}
+    for name, dur, lds, scr, vgpr, agpr, gx, gy, gz, wx in rows:
+        k = short_kernel_name(name)
+        e = stats.setdefault(k, {"n": 0, "tot": 0.0, "min": 1e30, "max": 0.0,
+                                 "res": (vgpr, agpr, lds, scr, wx)})
+        e["n"] += 1
+        e["tot"] += dur
+        e["min"] = min(e["min"], dur)
+        e["max"] = max(e["max"], dur)
+    if stats:
+        lines.append(f"{'kernel':60s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s} "
+                     f"{'min_us':>9s} {'max_us':>9s}  vgpr agpr lds scratch wg")
+        for k, e in sorted(stats.items(), key=lambda kv: -kv[1]["tot"]):
+            v, a, l, sc, wx = e["res"]
+            lines.append(f"{k:60s} {e['n']:6d} {e['tot'] / 1e6:10.3f} {e['tot'] / e['n'] / 1e3:10.2f} "
+                         f"{e['min'] / 1e3:9.2f} {e['max'] / 1e3:9.2f}  {v} {a} {l} {sc} {wx}")
+    try:
+        rows = list(cur.execute("select kernel_name, counter_name, value from counters_collection"))
+    except sqlite3.OperationalError:
+        rows = []
+    if rows:
+        agg = {}
+        for kn, cn, val in rows:
+            e = agg.setdefault((short_kernel_name(kn), cn), [0, 0.0])
+            e[0] += 1
+            e[1] += val
+        lines.append("")
+        lines.append(f"{'kernel':60s} {'counter':16s} {'dispatches':>10s} {'mean/dispatch':>16s}")
+        for (k, cn), (n, tot) in sorted(agg.items()):
+            lines.append(f"{k:60s} {cn:16s} {n:10d} {tot / n:16.1f}")
+    return "\n".join(lines)
+
+
 def calibrate_copy():
     import torch
     n = 1 << 30
@@ -128,9 +186,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--frames-per-block", type=int, default=0)
+    ap.add_argument("--frames", type=int, default=0,
+                    help="shorten the sub-integration (profiling runs only; not a bench figure)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--rocpd-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
     a = ap.parse_args()
+    if a.rocpd_summary:
+        print(rocpd_summary(a.rocpd_summary))
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU: the correlation path is built and measured on a "
               "single MI355X (multi-GPU sharding by subband x time is design-only).",
@@ -145,7 +209,7 @@ def main():
 
     log(f"generating workload {a.workload} on the GPU")
     t = time.perf_counter()
-    job, desc = make_job(a.workload)
+    job, desc = make_job(a.workload, a.frames)
     xcorr.job_to_device(job, "cuda:0")
     torch.cuda.synchronize()
     log(f"workload ready in {time.perf_counter() - t:.1f} s: {job.station_samples:.3e} "
@@ -167,7 +231,7 @@ def main():
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(a.steps)]
-    T = a.frames_per_block or min(1024, job.n_frames)
+    T = a.frames_per_block or min(2048, job.n_frames)
     blocks = -(-job.n_frames // T)
     corr.profile_begin(max_launches=a.steps * (3 * blocks + 4) + 16)
     torch.cuda.synchronize()
@@ -216,7 +280,7 @@ def main():
         "config": {"workload": desc, "stations": job.n_stations, "subbands": job.n_subbands,
                    "pols": job.n_pols, "channels": job.n_chan, "fft_len": job.N,
                    "frames": job.n_frames, "station_samples_per_step": ss,
-                   "frames_per_block": a.frames_per_block or min(1024, job.n_frames),
+                   "frames_per_block": a.frames_per_block or min(2048, job.n_frames),
                    "precision": "fp32", "parallelism": "single GPU"},
         "roofline": roof,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),

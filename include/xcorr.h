@@ -97,7 +97,7 @@ typedef struct {
   int64_t sub_start;           /* reference-time sample index of the sub-integration start */
   int64_t n_frames;            /* FFT frames in the sub-integration (>= 1) */
   int32_t precision;           /* XC_FP32 | XC_FP16_MFMA | XC_FP8_MFMA */
-  int32_t frames_per_block;    /* frames staged per F/X round, 0 = library default (1024);
+  int32_t frames_per_block;    /* frames staged per F/X round, 0 = library default (2048);
                                   at most 2048 */
 } xc_setup;
 
@@ -161,6 +161,23 @@ int xc_debug_unpack(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
 int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
                      int64_t frame0, int32_t n, void* spectra, void* workspace,
                      size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- tuning */
+/* Launch-shape parameters of the context (0 = library default / autotuned).
+ * They change speed only: results are identical for every setting except
+ * frames_per_block, which changes FP32 summation order (results stay within
+ * the FP32 path's tolerance). */
+typedef struct {
+  int32_t fstage_waves_per_simd;   /* F-stage occupancy target: 0, 1, 2, 3 or 4 */
+  int32_t xmac_frames_per_stage;   /* X-stage frames per LDS stage: 0, 2 or 4; 1 = no LDS
+                                      staging (inputs read from memory, one frame ahead) */
+  int32_t xmac_channels_per_wg;    /* X-stage channel tile: 0, 16, 32 or 64 */
+  int32_t frames_per_block;        /* used when a setup says 0: 0 (= 2048) or 1..2048 */
+  int32_t xmac_tiles_per_wg;       /* X-stage 4x4 input tiles per workgroup: 0 = all */
+} xc_tuning;
+
+int xc_set_tuning(xc_ctx* ctx, const xc_tuning* t);
+int xc_get_tuning(const xc_ctx* ctx, xc_tuning* t);
 
 /* ---------------------------------------------------------------- kernel timing */
 /* Kernel kinds for xc_profile_end. */

@@ -18,8 +18,11 @@ struct FGeom {
   static constexpr size_t lds_bytes = (size_t)G * lds_words<N>() * sizeof(float2);
 };
 
-template <int N>
-__global__ void __launch_bounds__(FGeom<N>::WG)
+// W = 0: no occupancy request; W > 0: ask the compiler for W waves per SIMD
+// (caps registers at 512 / W, trading spills for latency hiding).
+template <int N, int W>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
+                               amdgpu_waves_per_eu(W > 0 ? W : 1)))
     k_fstage(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
              float2* __restrict__ spec, int nf) {
@@ -40,40 +43,59 @@ __global__ void __launch_bounds__(FGeom<N>::WG)
   }
   const bool valid = r.valid != 0;
 
-  // payload words holding samples n = t + e T of this frame's window
+  // payload words holding samples n = t + e T of this frame's window; T is a
+  // multiple of 16, so all of a thread's samples share one field offset
   uint32_t wv[E];
-  int sh0[E];
+  int sh0 = 0;
   if (valid) {
     const FrameCursor c = make_cursor(J, r.base);
     const uint32_t* words = J.st[s].words;
 #pragma unroll
-    for (int e = 0; e < E; ++e) wv[e] = *sample_word(J, words, c, t + e * T, sh0[e]);
+    for (int e = 0; e < E; ++e) wv[e] = *sample_word(J, words, c, t + e * T);
+    sh0 = sample_shift(J, c, t);
   } else {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      wv[e] = 0u;
-      sh0[e] = 0;
-    }
+    for (int e = 0; e < E; ++e) wv[e] = 0u;
   }
   float2* lds = lds_all + g * lds_words<N>();
-  const float dN = (float)(r.d / (double)N);
   const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
+
+  // fractional-delay phasors of this thread's output bins k = t + r N/16:
+  // exp(2 pi i k d / N) = exp(2 pi i t d / N) * exp(2 pi i d / 16)^r
+  float2 fd[8];
+  {
+    const float dd = (float)r.d;
+    fd[0] = phasor_turns((float)t * dd * (1.0f / (float)N));
+    const float2 st = phasor_turns(dd * (1.0f / 16.0f));
+#pragma unroll
+    for (int rr = 1; rr < 8; ++rr) fd[rr] = cmul(fd[rr - 1], st);
+  }
+  const double nc0 = (double)(t - N / 2);     // centred index of the thread's first sample
+  constexpr double TD = (double)T;
 
   for (int in = 0; in < J.n_inputs; ++in) {
     const int sb = in / P, p = in - sb * P;
-    const int sh_stream = 2 * J.stream_map[in];
+    const int sh = sh0 + 2 * J.stream_map[in];
     PhaseRec ph;
     if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
     else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
+    // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
+    // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
+    // rho: its constant change 2 phi2 T^2), restarted exactly every E/2 samples
+    const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
     float2 v[E];
+    float2 z = make_float2(1.f, 0.f), w = make_float2(1.f, 0.f);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int n = t + e * T;
-      const float q = valid ? level_of((wv[e] >> (sh0[e] + sh_stream)) & 3u) : 0.0f;
-      const double dn = (double)(n - N / 2);
-      double x = fma(fma(ph.phi2, dn, ph.phi1), dn, ph.phi0);
-      x -= floor(x);
-      const float2 z = phasor_turns((float)x);
+      if (e % (E / 2) == 0) {
+        const double nc = nc0 + (double)e * TD;
+        z = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
+        w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
+      } else {
+        z = cmul(z, w);
+        w = cmul(w, rho);
+      }
+      const float q = valid ? level_of((wv[e] >> sh) & 3u) : 0.0f;
       v[e] = make_float2(q * z.x, q * z.y);
     }
     fft_forward<N>(v, lds, tw, t);
@@ -82,32 +104,41 @@ __global__ void __launch_bounds__(FGeom<N>::WG)
 #pragma unroll
       for (int rr = 0; rr < 8; ++rr) {
         const int k = t + rr * (N / 16);
-        float2 y = v[rr];
-        y = valid ? cmul(y, phasor_turns((float)k * dN)) : make_float2(0.f, 0.f);
-        out[k] = y;
+        out[k] = valid ? cmul(v[rr], fd[rr]) : make_float2(0.f, 0.f);
       }
     }
     __syncthreads();   // the next input reuses lds
   }
 }
 
-template <int N>
-static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* drec,
-                           const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                           hipStream_t s) {
+template <int N, int W>
+static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* drec,
+                            const PhaseRec* prec, const float2* tw, float2* spec, int nf,
+                            hipStream_t s) {
   using Gm = FGeom<N>;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fstage<N>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fstage<N, W>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)Gm::lds_bytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid((nf + Gm::G - 1) / Gm::G, n_stations);
-  hipLaunchKernelGGL(k_fstage<N>, grid, dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec, tw, spec,
-                     nf);
+  hipLaunchKernelGGL((k_fstage<N, W>), grid, dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec, tw,
+                     spec, nf);
   return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* drec,
+                           const PhaseRec* prec, const float2* tw, float2* spec, int nf,
+                           int waves, hipStream_t s) {
+  switch (waves) {
+    case 3: return launch_nw<N, 3>(job, n_stations, drec, prec, tw, spec, nf, s);
+    case 4: return launch_nw<N, 4>(job, n_stations, drec, prec, tw, spec, nf, s);
+    default: return launch_nw<N, 0>(job, n_stations, drec, prec, tw, spec, nf, s);
+  }
 }
 
 bool fstage_supported(int N) {
@@ -119,15 +150,15 @@ bool fstage_supported(int N) {
 
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
                          const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                         hipStream_t s) {
+                         int waves, hipStream_t s) {
   switch (N) {
-    case 256: return launch_n<256>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 512: return launch_n<512>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 1024: return launch_n<1024>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 2048: return launch_n<2048>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 4096: return launch_n<4096>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 8192: return launch_n<8192>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 16384: return launch_n<16384>(job, n_stations, drec, prec, tw, spec, nf, s);
+    case 256: return launch_n<256>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+    case 512: return launch_n<512>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+    case 1024: return launch_n<1024>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+    case 2048: return launch_n<2048>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+    case 4096: return launch_n<4096>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+    case 8192: return launch_n<8192>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+    case 16384: return launch_n<16384>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -70,19 +70,28 @@ hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int6
   return hipGetLastError();
 }
 
+// One workgroup per station pair (si <= sj): count frames valid for both.
 __global__ void k_weights(const DelayRec* __restrict__ drec, int S, int nf,
                           double* __restrict__ wst) {
-  const int si = blockIdx.x, sj = threadIdx.x;
-  if (sj < si || sj >= S) return;
+  const int si = blockIdx.x, sj = blockIdx.y;
+  if (sj < si) return;
+  __shared__ int part[256];
   int cnt = 0;
-  for (int f = 0; f < nf; ++f)
+  for (int f = threadIdx.x; f < nf; f += blockDim.x)
     cnt += drec[(size_t)si * nf + f].valid & drec[(size_t)sj * nf + f].valid;
-  wst[si * S + sj] += (double)cnt;
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) wst[si * S + sj] += (double)part[0];
 }
 
 hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* wst,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_weights, dim3(n_stations), dim3(64), 0, s, drec, n_stations, nf, wst);
+  hipLaunchKernelGGL(k_weights, dim3(n_stations, n_stations), dim3(256), 0, s, drec, n_stations,
+                     nf, wst);
   return hipGetLastError();
 }
 
@@ -135,9 +144,8 @@ __global__ void k_debug_unpack(const DevJob* __restrict__ job, const DelayRec* _
     return;
   }
   const FrameCursor c = make_cursor(J, r.base);
-  int sh0;
-  const uint32_t w = *sample_word(J, J.st[station].words, c, n, sh0);
-  out[n] = level_of((w >> (sh0 + 2 * J.stream_map[input])) & 3u);
+  const uint32_t w = *sample_word(J, J.st[station].words, c, n);
+  out[n] = level_of((w >> (sample_shift(J, c, n) + 2 * J.stream_map[input])) & 3u);
 }
 
 hipError_t launch_debug_unpack(const DevJob* job, const DelayRec* drec, int nf, int station,

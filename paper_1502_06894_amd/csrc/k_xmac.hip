@@ -28,13 +28,19 @@ __device__ inline void tile_of(int tile, int ng, int& gi, int& gj) {
 
 __device__ inline int bl_index(int i, int j, int M) { return i * M - (i * (i - 1)) / 2 + (j - i); }
 
-// LDS row stride: KC channels plus one float2 so that rows start on different banks.
-template <int KC>
-__global__ void k_xmac(const DevJob* __restrict__ job, const float2* __restrict__ spec,
-                       double2* __restrict__ vacc, int nf, int FB, int tiles_per_wg,
-                       int zchunks, int frames_per_split, size_t slot_stride) {
-  extern __shared__ float2 sh[];   // [FB][Mp][KC + 1]
-  constexpr int RS = KC + 1;
+// LDS layout per stage: [FB frames][Mp inputs][RS] float2 with RS = KC + 2, so
+// rows start on different banks and stay 16-byte aligned.  Two stages are
+// double-buffered: the global loads of stage s+1 are in flight (registers)
+// while stage s is multiplied out of LDS.
+template <int KC, int FB, int MAXL>
+__global__ void __launch_bounds__(1024)
+    k_xmac(const DevJob* __restrict__ job, const float2* __restrict__ spec,
+           double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
+           int frames_per_split, size_t slot_stride) {
+  extern __shared__ float4 sh4[];
+  constexpr int RS = KC + 2;          // float2 per LDS row
+  constexpr int RS4 = RS / 2;         // float4 per LDS row
+  constexpr int KC4 = KC / 2;
   const DevJob& J = *job;
   const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
@@ -48,16 +54,13 @@ __global__ void k_xmac(const DevJob* __restrict__ job, const float2* __restrict_
   const int c = threadIdx.x % KC;
   const int tile = zc * tiles_per_wg + threadIdx.x / KC;
   const bool active = (int)(threadIdx.x / KC) < tiles_per_wg && tile < ntiles;
+  const int nthr = blockDim.x;
+  const int stage4 = FB * Mp * RS4;   // float4 per stage buffer
   int gi = 0, gj = 0;
   if (active) tile_of(tile, ng, gi, gj);
 
-  // zero the padding rows once
-  const int pad_rows = Mp - M;
-  for (int q = threadIdx.x; q < FB * pad_rows * KC; q += blockDim.x) {
-    const int fb = q / (pad_rows * KC);
-    const int rem = q - fb * pad_rows * KC;
-    sh[(fb * Mp + M + rem / KC) * RS + rem % KC] = make_float2(0.f, 0.f);
-  }
+  // zero both stages once (covers the padding rows Mp > M)
+  for (int q = threadIdx.x; q < 2 * stage4; q += nthr) sh4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
 
   float2 acc[kGroup][kGroup];
 #pragma unroll
@@ -65,24 +68,54 @@ __global__ void k_xmac(const DevJob* __restrict__ job, const float2* __restrict_
 #pragma unroll
     for (int b = 0; b < kGroup; ++b) acc[a][b] = make_float2(0.f, 0.f);
 
-  const float2* src = spec + (size_t)sb * nf * M * n_chan + k0;
+  const float4* src = reinterpret_cast<const float4*>(spec + (size_t)sb * nf * M * n_chan + k0);
+  const int row4 = n_chan / 2;        // float4 per spectrum row
+  float4 pre[MAXL];
+  auto gload = [&](int f0) {
+    const int nfb = min(FB, fz - f0);
+    const int n = nfb * M * KC4;
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) {
+      const int q = threadIdx.x + i * nthr;
+      if (q < n) {
+        const int row = q / KC4, cc = q - row * KC4;
+        pre[i] = src[(size_t)(f0 * M + row) * row4 + cc];
+      }
+    }
+  };
+  auto lstore = [&](int f0, int buf) {
+    const int nfb = min(FB, fz - f0);
+    const int n = nfb * M * KC4;
+#pragma unroll
+    for (int i = 0; i < MAXL; ++i) {
+      const int q = threadIdx.x + i * nthr;
+      if (q < n) {
+        const int row = q / KC4, cc = q - row * KC4;
+        const int fb = row / M, m = row - fb * M;
+        sh4[buf * stage4 + (fb * Mp + m) * RS4 + cc] = pre[i];
+      }
+    }
+  };
+
+  __syncthreads();
+  if (fa < fz) {
+    gload(fa);
+    lstore(fa, 0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int f0 = fa; f0 < fz; f0 += FB) {
     const int nfb = min(FB, fz - f0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < nfb * M * KC; q += blockDim.x) {
-      const int row = q / KC;                 // fb * M + m
-      const int cc = q - row * KC;
-      const int fb = row / M, m = row - fb * M;
-      sh[(fb * Mp + m) * RS + cc] = src[((size_t)(f0 + fb) * M + m) * n_chan + cc];
-    }
-    __syncthreads();
+    const bool more = f0 + FB < fz;
+    if (more) gload(f0 + FB);
     if (active) {
+      const float2* shb = reinterpret_cast<const float2*>(sh4 + buf * stage4);
       for (int fb = 0; fb < nfb; ++fb) {
         float2 a[kGroup], b[kGroup];
 #pragma unroll
         for (int x = 0; x < kGroup; ++x) {
-          a[x] = sh[(fb * Mp + gi * kGroup + x) * RS + c];
-          b[x] = sh[(fb * Mp + gj * kGroup + x) * RS + c];
+          a[x] = shb[(fb * Mp + gi * kGroup + x) * RS + c];
+          b[x] = shb[(fb * Mp + gj * kGroup + x) * RS + c];
         }
 #pragma unroll
         for (int x = 0; x < kGroup; ++x)
@@ -94,6 +127,9 @@ __global__ void k_xmac(const DevJob* __restrict__ job, const float2* __restrict_
           }
       }
     }
+    if (more) lstore(f0 + FB, buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   if (!active || fa >= fz) return;
   double2* slot = vacc + (size_t)split * slot_stride;
@@ -112,49 +148,194 @@ __global__ void k_xmac(const DevJob* __restrict__ job, const float2* __restrict_
     }
 }
 
-int xmac_splits(int nf) { return (nf + kXmacFramesPerSplit - 1) / kXmacFramesPerSplit; }
+// Barrier-free variant: each thread reads its 2 x 4 inputs of every frame
+// straight from memory (the same workgroup's other tiles re-read them from L1),
+// one frame ahead in registers.  A workgroup is all tiles of KC channels.
+template <int KC>
+__global__ void __launch_bounds__(1024)
+    k_xmac_direct(const DevJob* __restrict__ job, const float2* __restrict__ spec,
+                  double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
+                  int frames_per_split, size_t slot_stride) {
+  const DevJob& J = *job;
+  const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  const int ng = Mp / kGroup;
+  const int ntiles = ng * (ng + 1) / 2;
+  const int sb = blockIdx.y;
+  const int k0 = blockIdx.x * KC;
+  const int zc = blockIdx.z % zchunks, split = blockIdx.z / zchunks;
+  const int fa = split * frames_per_split;
+  const int fz = min(nf, fa + frames_per_split);
+  const int c = threadIdx.x % KC;
+  const int tile = zc * tiles_per_wg + threadIdx.x / KC;
+  if ((int)(threadIdx.x / KC) >= tiles_per_wg || tile >= ntiles || fa >= fz) return;
+  int gi, gj;
+  tile_of(tile, ng, gi, gj);
+  // inputs beyond M read row M-1 (their products are never stored)
+  int ra[kGroup], rb[kGroup];
+#pragma unroll
+  for (int x = 0; x < kGroup; ++x) {
+    ra[x] = min(gi * kGroup + x, M - 1);
+    rb[x] = min(gj * kGroup + x, M - 1);
+  }
+  const float2* src = spec + (size_t)sb * nf * M * n_chan + k0 + c;
+  const size_t fstride = (size_t)M * n_chan;
 
-hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
-                       const float2* spec, double2* vacc, size_t slot_stride, int nf,
-                       hipStream_t s) {
+  float2 acc[kGroup][kGroup];
+#pragma unroll
+  for (int a = 0; a < kGroup; ++a)
+#pragma unroll
+    for (int b = 0; b < kGroup; ++b) acc[a][b] = make_float2(0.f, 0.f);
+
+  float2 a[kGroup], b[kGroup], an[kGroup], bn[kGroup];
+  const float2* p = src + (size_t)fa * fstride;
+#pragma unroll
+  for (int x = 0; x < kGroup; ++x) {
+    a[x] = p[(size_t)ra[x] * n_chan];
+    b[x] = p[(size_t)rb[x] * n_chan];
+  }
+  for (int f = fa; f < fz; ++f) {
+    if (f + 1 < fz) {
+      const float2* q = p + fstride;
+#pragma unroll
+      for (int x = 0; x < kGroup; ++x) {
+        an[x] = q[(size_t)ra[x] * n_chan];
+        bn[x] = q[(size_t)rb[x] * n_chan];
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < kGroup; ++x)
+#pragma unroll
+      for (int y = 0; y < kGroup; ++y) {
+        acc[x][y].x = fmaf(a[x].x, b[y].x, fmaf(a[x].y, b[y].y, acc[x][y].x));
+        acc[x][y].y = fmaf(a[x].y, b[y].x, fmaf(-a[x].x, b[y].y, acc[x][y].y));
+      }
+#pragma unroll
+    for (int x = 0; x < kGroup; ++x) {
+      a[x] = an[x];
+      b[x] = bn[x];
+    }
+    p += fstride;
+  }
+  double2* slot = vacc + (size_t)split * slot_stride;
+#pragma unroll
+  for (int x = 0; x < kGroup; ++x)
+#pragma unroll
+    for (int y = 0; y < kGroup; ++y) {
+      const int i = gi * kGroup + x, j = gj * kGroup + y;
+      if (i <= j && j < M) {
+        double2* o = slot + ((size_t)sb * nbl + bl_index(i, j, M)) * n_chan + k0 + c;
+        double2 v = *o;
+        v.x += (double)acc[x][y].x;
+        v.y += (double)acc[x][y].y;
+        *o = v;
+      }
+    }
+}
+
+static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subbands,
+                                const float2* spec, double2* vacc, size_t slot_stride, int nf,
+                                int kc_req, int tpw_req, hipStream_t s) {
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
   const int n_splits = xmac_splits(nf);
   const int fps = (nf + n_splits - 1) / n_splits;
-  // widest channel tile that still gives a few workgroups per compute unit
-  int KC = 16;
-  for (int kc : {64, 32}) {
-    int tpw = 1024 / kc < ntiles ? 1024 / kc : ntiles;
-    long wgs = (long)(n_chan / kc) * n_subbands * ((ntiles + tpw - 1) / tpw) * n_splits;
-    if (kc <= n_chan && wgs >= 1024) {
-      KC = kc;
-      break;
-    }
-  }
-  int tiles_per_wg = 256 / KC > 1 ? 256 / KC : 1;    // 256-thread workgroups
+  int KC = (kc_req == 16 || kc_req == 32 || kc_req == 64) ? kc_req : 64;
+  if (KC > n_chan) KC = n_chan;
+  int tiles_per_wg = tpw_req > 0 ? tpw_req : 1024 / KC;
+  if (tiles_per_wg > 1024 / KC) tiles_per_wg = 1024 / KC;
   if (tiles_per_wg > ntiles) tiles_per_wg = ntiles;
   const int zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
-  int FB = 8;
-  while (FB > 1 && (size_t)FB * Mp * (KC + 1) * sizeof(float2) > 32768) FB /= 2;
-  const size_t lds = (size_t)FB * Mp * (KC + 1) * sizeof(float2);
   dim3 grid(n_chan / KC, n_subbands, zchunks * n_splits);
   dim3 block(KC * tiles_per_wg);
   switch (KC) {
     case 64:
-      hipLaunchKernelGGL(k_xmac<64>, grid, block, lds, s, job, spec, vacc, nf, FB, tiles_per_wg,
+      hipLaunchKernelGGL(k_xmac_direct<64>, grid, block, 0, s, job, spec, vacc, nf, tiles_per_wg,
                          zchunks, fps, slot_stride);
       break;
     case 32:
-      hipLaunchKernelGGL(k_xmac<32>, grid, block, lds, s, job, spec, vacc, nf, FB, tiles_per_wg,
+      hipLaunchKernelGGL(k_xmac_direct<32>, grid, block, 0, s, job, spec, vacc, nf, tiles_per_wg,
                          zchunks, fps, slot_stride);
       break;
     default:
-      hipLaunchKernelGGL(k_xmac<16>, grid, block, lds, s, job, spec, vacc, nf, FB, tiles_per_wg,
+      hipLaunchKernelGGL(k_xmac_direct<16>, grid, block, 0, s, job, spec, vacc, nf, tiles_per_wg,
                          zchunks, fps, slot_stride);
       break;
   }
   return hipGetLastError();
+}
+
+int xmac_splits(int nf) { return (nf + kXmacFramesPerSplit - 1) / kXmacFramesPerSplit; }
+
+template <int FB>
+static hipError_t launch_fb(const DevJob* job, int M, int n_chan, int n_subbands,
+                            const float2* spec, double2* vacc, size_t slot_stride, int nf,
+                            int kc_req, int tpw_req, hipStream_t s) {
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  const int ng = Mp / kGroup;
+  const int ntiles = ng * (ng + 1) / 2;
+  const int n_splits = xmac_splits(nf);
+  const int fps = (nf + n_splits - 1) / n_splits;
+  auto lds_of = [&](int kc) { return 2 * (size_t)FB * Mp * (kc + 2) * sizeof(float2); };
+  // widest channel tile that fits 64 KB of LDS and still gives a few
+  // workgroups per compute unit; else the narrowest (unless one is requested)
+  int KC = 16;
+  if (kc_req == 16 || kc_req == 32 || kc_req == 64) {
+    KC = kc_req <= n_chan ? kc_req : 16;
+  } else {
+    for (int kc : {64, 32}) {
+      const int tpw = 1024 / kc < ntiles ? 1024 / kc : ntiles;
+      const long wgs = (long)(n_chan / kc) * n_subbands * ((ntiles + tpw - 1) / tpw) * n_splits;
+      if (kc <= n_chan && wgs >= 1024 && lds_of(kc) <= 65536) {
+        KC = kc;
+        break;
+      }
+    }
+  }
+  int tiles_per_wg = tpw_req > 0 && tpw_req < 1024 / KC ? tpw_req : 1024 / KC;
+  // enough threads that each stages at most 16 float4 per LDS stage
+  const int min_tpw = (FB * M * (KC / 2) + 16 * KC - 1) / (16 * KC);
+  if (tiles_per_wg < min_tpw) tiles_per_wg = min_tpw;
+  if (tiles_per_wg > ntiles) tiles_per_wg = ntiles;
+  const int zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
+  const int nthr = KC * tiles_per_wg;
+  const size_t lds = lds_of(KC);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  // float4 loads per thread per stage (the kernels hold up to MAXL in registers)
+  const int per_thr = (FB * M * (KC / 2) + nthr - 1) / nthr;
+  dim3 grid(n_chan / KC, n_subbands, zchunks * n_splits);
+  dim3 block(nthr);
+#define XMAC_LAUNCH(KCV, MAXLV)                                                                 \
+  do {                                                                                         \
+    auto kern = k_xmac<KCV, FB, MAXLV>;                                                        \
+    if (lds > 65536) {                                                                         \
+      hipError_t e = hipFuncSetAttribute((const void*)kern,                                    \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);\
+      if (e != hipSuccess) return e;                                                           \
+    }                                                                                          \
+    hipLaunchKernelGGL(kern, grid, block, lds, s, job, spec, vacc, nf, tiles_per_wg, zchunks,  \
+                       fps, slot_stride);                                                      \
+  } while (0)
+  if (per_thr <= 4) {
+    if (KC == 64) XMAC_LAUNCH(64, 4); else if (KC == 32) XMAC_LAUNCH(32, 4); else XMAC_LAUNCH(16, 4);
+  } else if (per_thr <= 16) {
+    if (KC == 64) XMAC_LAUNCH(64, 16); else if (KC == 32) XMAC_LAUNCH(32, 16); else XMAC_LAUNCH(16, 16);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef XMAC_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
+                       const float2* spec, double2* vacc, size_t slot_stride, int nf, int fb,
+                       int kc, int tpw, hipStream_t s) {
+  if (fb == 1)
+    return launch_direct(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
+  if (fb == 4)
+    return launch_fb<4>(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
+  return launch_fb<2>(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
 }
 
 }  // namespace xc

@@ -165,15 +165,19 @@ __device__ inline FrameCursor make_cursor(const DevJob& j, int64_t base) {
   return c;
 }
 
+// Payload word holding per-stream sample base + n (window start in cursor c).
 __device__ inline const uint32_t* sample_word(const DevJob& j, const uint32_t* words,
-                                              const FrameCursor& c, int n, int& shift0) {
+                                              const FrameCursor& c, int n) {
   const uint32_t ip = (uint32_t)(c.ip0 + n);               // < spf + N <= 72768
   const uint32_t q = __umulhi(ip, j.spf_magic);            // ip / spf
   const uint32_t in = ip - q * (uint32_t)j.spf;
-  const uint32_t w = in >> j.spw_log2;
-  const uint32_t sub = in & ((1u << j.spw_log2) - 1u);
-  shift0 = (int)(2u * sub * (uint32_t)j.C);
-  return words + (c.fm0 + (int64_t)q) * kFrameWords + kHeaderWords + w;
+  return words + (c.fm0 + (int64_t)q) * kFrameWords + kHeaderWords + (in >> j.spw_log2);
+}
+
+// Bit offset of stream 0's field for sample base + n.  spf is a multiple of the
+// samples per word, so the offset depends only on (ip0 + n) mod (16 / C).
+__device__ inline int sample_shift(const DevJob& j, const FrameCursor& c, int n) {
+  return (int)(2u * (((uint32_t)(c.ip0 + n)) & ((1u << j.spw_log2) - 1u)) * (uint32_t)j.C);
 }
 
 __device__ inline float level_of(uint32_t code) {
@@ -187,6 +191,9 @@ __device__ inline float level_of(uint32_t code) {
 __device__ inline float2 phasor_turns(float x) {
   return make_float2(__builtin_amdgcn_cosf(x), __builtin_amdgcn_sinf(x));
 }
+
+// x - floor(x) of a double, as float (in [0, 1]).
+__device__ inline float frac_f(double x) { return (float)(x - floor(x)); }
 
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

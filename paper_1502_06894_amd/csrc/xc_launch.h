@@ -19,18 +19,21 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
                          DelayRec* drec, PhaseRec* prec, hipStream_t s);
 // A2-A5: spectra [n_subbands][nf][M][n_chan] for the block's frames.
+// waves: occupancy target of the F kernel (0 = compiler's choice, else 2..4).
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
                          const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                         hipStream_t s);
+                         int waves, hipStream_t s);
 // Frames one X workgroup accumulates in FP32 before adding to its FP64 slot.
 constexpr int kXmacFramesPerSplit = 256;
 // Accumulator slots a block of nf frames uses (frames split kXmacFramesPerSplit at a time).
 int xmac_splits(int nf);
 // A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
 // (double2), slot_stride elements apart.
+// fb: frames per LDS stage (2 or 4, 0 = default); kc: channel tile (16/32/64, 0 = auto).
+// tpw: 4x4 tiles per workgroup (0 = all that fit in 1024 threads).
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
-                       const float2* spec, double2* vacc, size_t slot_stride, int nf,
-                       hipStream_t s);
+                       const float2* spec, double2* vacc, size_t slot_stride, int nf, int fb,
+                       int kc, int tpw, hipStream_t s);
 // Frames of the block valid for both stations of each station pair: wst[si][sj] += count.
 hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* wst,
                           hipStream_t s);

@@ -30,6 +30,7 @@ struct Timed {
 
 struct xc_ctx {
   int device = 0;
+  xc_tuning tune = {0, 0, 0, 0, 0};
   bool profiling = false;
   std::vector<Timed> prof;        // event pairs, reused across profile sessions
   size_t prof_used = 0;
@@ -91,10 +92,12 @@ struct Layout {
 };
 
 constexpr int kMaxBlockFrames = 2048;
-constexpr int kDefaultBlockFrames = 1024;
+constexpr int kDefaultBlockFrames = 2048;
 
-int block_frames(const xc_setup* s) {
-  int64_t T = s->frames_per_block > 0 ? s->frames_per_block : kDefaultBlockFrames;
+int block_frames(const xc_setup* s, const xc_ctx* c) {
+  int64_t T = s->frames_per_block > 0 ? s->frames_per_block
+              : (c && c->tune.frames_per_block > 0) ? c->tune.frames_per_block
+                                                     : kDefaultBlockFrames;
   if (T > s->n_frames) T = s->n_frames;
   return (int)T;
 }
@@ -148,11 +151,11 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
   return XC_OK;
 }
 
-Layout layout_of(const xc_setup* s, const xc_station* st) {
+Layout layout_of(const xc_setup* s, const xc_station* st, const xc_ctx* c) {
   Layout L;
   const int S = s->n_stations, nsb = s->n_subbands, M = S * s->n_pols;
   const size_t nbl = (size_t)M * (M + 1) / 2;
-  L.T = block_frames(s);
+  L.T = block_frames(s, c);
   L.desc_bytes = sizeof(DevJob) + (size_t)S * sizeof(DevStation) +
                  (size_t)S * nsb * (kMaxPolyDeg + 1) * sizeof(double);
   size_t off = 0;
@@ -252,7 +255,7 @@ int prepare(xc_ctx* c, const xc_setup* s, const xc_station* st, void* workspace,
   if (!c) return XC_E_INVAL;
   int rc = validate(c, s, st);
   if (rc != XC_OK) return rc;
-  L = layout_of(s, st);
+  L = layout_of(s, st, c);
   if (!workspace || ws_bytes < L.total)
     return fail(c, XC_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
   hipError_t e = hipSetDevice(c->device);
@@ -354,7 +357,7 @@ int xc_validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
 
 size_t xc_workspace_bytes(const xc_ctx* c, const xc_setup* s, const xc_station* st) {
   if (validate(const_cast<xc_ctx*>(c), s, st) != XC_OK) return 0;
-  return layout_of(s, st).total;
+  return layout_of(s, st, c).total;
 }
 
 int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
@@ -386,10 +389,15 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
     });
     if (e != hipSuccess) return hip_fail(c, e, "delays");
     e = timed(c, XC_K_FSTAGE, stream,
-              [&] { return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nf, stream); });
+              [&] {
+                return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nf,
+                                     c->tune.fstage_waves_per_simd, stream);
+              });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
     e = timed(c, XC_K_XMAC, stream, [&] {
-      return launch_xmac(dj, M, s->n_chan, nsb, spec, vacc, L.slot_stride, nf, stream);
+      return launch_xmac(dj, M, s->n_chan, nsb, spec, vacc, L.slot_stride, nf,
+                         c->tune.xmac_frames_per_stage, c->tune.xmac_channels_per_wg,
+                         c->tune.xmac_tiles_per_wg, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "xmac");
   }
@@ -399,6 +407,26 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
                            stream);
   });
   if (e != hipSuccess) return hip_fail(c, e, "finalise");
+  return XC_OK;
+}
+
+int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
+  if (!c || !t) return XC_E_INVAL;
+  const bool ok = t->fstage_waves_per_simd >= 0 && t->fstage_waves_per_simd <= 4 &&
+                  (t->xmac_frames_per_stage >= 0 && t->xmac_frames_per_stage <= 4 &&
+                   t->xmac_frames_per_stage != 3) &&
+                  (t->xmac_channels_per_wg == 0 || t->xmac_channels_per_wg == 16 ||
+                   t->xmac_channels_per_wg == 32 || t->xmac_channels_per_wg == 64) &&
+                  t->frames_per_block >= 0 && t->frames_per_block <= kMaxBlockFrames &&
+                  t->xmac_tiles_per_wg >= 0 && t->xmac_tiles_per_wg <= 64;
+  if (!ok) return fail(c, XC_E_INVAL, "tuning value out of range");
+  c->tune = *t;
+  return XC_OK;
+}
+
+int xc_get_tuning(const xc_ctx* c, xc_tuning* t) {
+  if (!c || !t) return XC_E_INVAL;
+  *t = c->tune;
   return XC_OK;
 }
 
@@ -517,7 +545,7 @@ int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t
   hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, stream);
   if (e == hipSuccess)
     e = launch_fstage(2 * s->n_chan, dj, s->n_stations, drec, prec, c->d_tw,
-                      static_cast<float2*>(spectra), n, stream);
+                      static_cast<float2*>(spectra), n, c->tune.fstage_waves_per_simd, stream);
   return e == hipSuccess ? XC_OK : hip_fail(c, e, "debug_spectra");
 }
 

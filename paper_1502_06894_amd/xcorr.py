@@ -43,6 +43,12 @@ class XcOutput(C.Structure):
     _fields_ = [("vis", C.c_void_p), ("weight", C.c_void_p)]
 
 
+class XcTuning(C.Structure):
+    _fields_ = [("fstage_waves_per_simd", C.c_int32), ("xmac_frames_per_stage", C.c_int32),
+                ("xmac_channels_per_wg", C.c_int32), ("frames_per_block", C.c_int32),
+                ("xmac_tiles_per_wg", C.c_int32)]
+
+
 class XcError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"xcorr error {code}: {msg}")
@@ -76,6 +82,8 @@ def load_library() -> C.CDLL:
                                           C.c_int32, C.c_int64, P, P, C.c_size_t, P]),
             "xc_debug_spectra": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
                                            C.c_int64, C.c_int32, P, P, C.c_size_t, P]),
+            "xc_set_tuning": (C.c_int, [P, C.POINTER(XcTuning)]),
+            "xc_get_tuning": (C.c_int, [P, C.POINTER(XcTuning)]),
             "xc_profile_begin": (C.c_int, [P, C.c_int32]),
             "xc_profile_end": (C.c_int, [P, P, P]),
         }
@@ -203,6 +211,20 @@ class Correlator:
                                                  C.byref(o), workspace.data_ptr(),
                                                  workspace.numel(), _stream_ptr(stream)))
         return vis, w
+
+    def set_tuning(self, **kw):
+        """Set launch-shape parameters (fstage_waves_per_simd, xmac_frames_per_stage,
+        xmac_channels_per_wg, frames_per_block); unspecified ones keep their value."""
+        t = XcTuning()
+        self._check(self.lib.xc_get_tuning(self.ctx, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        self._check(self.lib.xc_set_tuning(self.ctx, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = XcTuning()
+        self._check(self.lib.xc_get_tuning(self.ctx, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in XcTuning._fields_}
 
     def profile_begin(self, max_launches: int = 8192):
         """Time every kernel launch of this context with HIP events on its stream."""

@@ -186,3 +186,31 @@ def test_deterministic_repeat(xc, corr):
     a = corr.correlate(job)[0].clone()
     for _ in range(3):
         assert torch.equal(corr.correlate(job)[0], a)
+
+
+def test_tuning_variants_bit_identical(xc, corr):
+    """Launch-shape variants change speed only: visibilities must be bit-identical."""
+    job = configs.small_job(n_stations=5, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=300)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    ref = None
+    try:
+        for tune in [dict(), dict(xmac_frames_per_stage=1), dict(xmac_frames_per_stage=2),
+                     dict(xmac_frames_per_stage=4, xmac_channels_per_wg=16),
+                     dict(xmac_frames_per_stage=1, xmac_channels_per_wg=32),
+                     dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=1),
+                     dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=3, xmac_channels_per_wg=16),
+                     dict(fstage_waves_per_simd=3), dict(fstage_waves_per_simd=4)]:
+            base = dict(fstage_waves_per_simd=0, xmac_frames_per_stage=0, xmac_channels_per_wg=0,
+                        xmac_tiles_per_wg=0)
+            base.update(tune)
+            corr.set_tuning(**base)
+            vis, w = corr.correlate(job, frames_per_block=300)
+            vis = vis.cpu()
+            if ref is None:
+                ref = vis
+                assert rel_l2(vis.numpy(), V) < TOL
+            assert torch.equal(vis, ref), tune
+    finally:
+        corr.set_tuning(fstage_waves_per_simd=0, xmac_frames_per_stage=0, xmac_channels_per_wg=0,
+                        xmac_tiles_per_wg=0)
