@@ -18,14 +18,38 @@ struct FGeom {
   static constexpr size_t lds_bytes = (size_t)G * lds_words<N>() * sizeof(float2);
 };
 
+// Spectrum element written by the F stage: FP32 complex, or for the MFMA X
+// path the power-of-two-scaled value as FP16 (Re, Im) or OCP e4m3 (Re, Im).
+template <int OUT>
+__device__ inline void put_spec(void* spec, size_t idx, float2 y, int e) {
+  if constexpr (OUT == kOutF32) {
+    static_cast<float2*>(spec)[idx] = y;
+  } else if constexpr (OUT == kOutF16) {
+    const float sx = ldexpf(y.x, e), sy = ldexpf(y.y, e);
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    h2 h;
+    h.x = (_Float16)sx;
+    h.y = (_Float16)sy;
+    static_cast<h2*>(spec)[idx] = h;
+  } else {
+    // the conversion maps overflow to NaN: saturate at the e4m3 maximum first
+    const float sx = fminf(fmaxf(ldexpf(y.x, e), -448.f), 448.f);
+    const float sy = fminf(fmaxf(ldexpf(y.y, e), -448.f), 448.f);
+    const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(sx, sy, 0, false);
+    static_cast<uint16_t*>(spec)[idx] = (uint16_t)(pk & 0xffff);
+  }
+}
+
 // W = 0: no occupancy request; W > 0: ask the compiler for W waves per SIMD
 // (caps registers at 512 / W, trading spills for latency hiding).
-template <int N, int W>
+// OUT: spectrum element type (kOutF32, kOutF16, kOutF8); for the low-precision
+// outputs `scale_exp` [n_sb][M][n_chan] holds the power-of-two exponents.
+template <int N, int W, int OUT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
                                amdgpu_waves_per_eu(W > 0 ? W : 1)))
     k_fstage(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
-             float2* __restrict__ spec, int nf) {
+             void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf) {
   constexpr int T = FGeom<N>::T, E = FGeom<N>::E, G = FGeom<N>::G;
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
@@ -100,44 +124,52 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     }
     fft_forward<N>(v, lds, tw, t);
     if (in_blk) {
-      float2* out = spec + ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+      const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+      const int8_t* ex = OUT == kOutF32 ? nullptr
+                                        : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
 #pragma unroll
       for (int rr = 0; rr < 8; ++rr) {
         const int k = t + rr * (N / 16);
-        out[k] = valid ? cmul(v[rr], fd[rr]) : make_float2(0.f, 0.f);
+        const float2 y = valid ? cmul(v[rr], fd[rr]) : make_float2(0.f, 0.f);
+        put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
       }
     }
     __syncthreads();   // the next input reuses lds
   }
 }
 
-template <int N, int W>
+template <int N, int W, int OUT>
 static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* drec,
-                            const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                            hipStream_t s) {
+                            const PhaseRec* prec, const float2* tw, void* spec,
+                            const int8_t* scale_exp, int nf, hipStream_t s) {
   using Gm = FGeom<N>;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fstage<N, W>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_fstage<N, W, OUT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)Gm::lds_bytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   dim3 grid((nf + Gm::G - 1) / Gm::G, n_stations);
-  hipLaunchKernelGGL((k_fstage<N, W>), grid, dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec, tw,
-                     spec, nf);
+  hipLaunchKernelGGL((k_fstage<N, W, OUT>), grid, dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec,
+                     tw, spec, scale_exp, nf);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* drec,
-                           const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                           int waves, hipStream_t s) {
+                           const PhaseRec* prec, const float2* tw, void* spec,
+                           const int8_t* scale_exp, int nf, int waves, int out, hipStream_t s) {
+  if (out == kOutF16)
+    return launch_nw<N, 0, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, s);
+  if (out == kOutF8)
+    return launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, s);
   switch (waves) {
-    case 3: return launch_nw<N, 3>(job, n_stations, drec, prec, tw, spec, nf, s);
-    case 4: return launch_nw<N, 4>(job, n_stations, drec, prec, tw, spec, nf, s);
-    default: return launch_nw<N, 0>(job, n_stations, drec, prec, tw, spec, nf, s);
+    case 3: return launch_nw<N, 3, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, s);
+    case 4: return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, s);
+    default:
+      return launch_nw<N, 0, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, s);
   }
 }
 
@@ -149,16 +181,15 @@ bool fstage_supported(int N) {
 }
 
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
-                         const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                         int waves, hipStream_t s) {
+                         const PhaseRec* prec, const float2* tw, void* spec,
+                         const int8_t* scale_exp, int nf, int waves, int out, hipStream_t s) {
   switch (N) {
-    case 256: return launch_n<256>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
-    case 512: return launch_n<512>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
-    case 1024: return launch_n<1024>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
-    case 2048: return launch_n<2048>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
-    case 4096: return launch_n<4096>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
-    case 8192: return launch_n<8192>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
-    case 16384: return launch_n<16384>(job, n_stations, drec, prec, tw, spec, nf, waves, s);
+#define XC_FCASE(NN)                                                                      \
+  case NN:                                                                                \
+    return launch_n<NN>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, waves, out, s);
+    XC_FCASE(256) XC_FCASE(512) XC_FCASE(1024) XC_FCASE(2048) XC_FCASE(4096) XC_FCASE(8192)
+    XC_FCASE(16384)
+#undef XC_FCASE
     default: return hipErrorInvalidValue;
   }
 }

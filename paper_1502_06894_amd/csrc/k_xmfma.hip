@@ -1,0 +1,232 @@
+// A7: X stage on the matrix cores for FP16 / FP8 spectra.
+//
+// Per channel, the block's spectra of the M <= 32 inputs form Z = [Re X; Im X]
+// (2M x frames, each input scaled by a power of two before rounding).  The
+// Hermitian product splits into real products over frames:
+//   V_re = Re Re^T + Im Im^T,   V_im = Im Re^T - (Im Re^T)^T,
+// so three 32x32 MFMA tiles per channel (G11 = Re Re^T, G22 = Im Im^T,
+// G21 = Im Re^T) accumulate in FP32 with K = frames.  A workgroup owns KC
+// channels of one subband; spectra arrive in the F stage's [frame][input]
+// [channel] order and are transposed into LDS as [channel word][input][frame]
+// so that each lane's MFMA operand (4 FP16 or 8 FP8 consecutive frames of one
+// input) is a single 16-byte LDS read.  After the block, G21 is transposed
+// through LDS, every element is unscaled by 2^-(e_i + e_j) and added to the
+// FP64 accumulator slot of the FP32 path.
+#include "xc_launch.h"
+
+namespace xc {
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+__global__ void k_scales(const float2* __restrict__ spec, int n_sb, int nf, int M, int n_chan,
+                         int target_log2, int8_t* __restrict__ scale_exp) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // (sb, m, k)
+  const size_t total = (size_t)n_sb * M * n_chan;
+  if (i >= total) return;
+  const int k = (int)(i % n_chan);
+  const int m = (int)((i / n_chan) % M);
+  const int sb = (int)(i / ((size_t)n_chan * M));
+  double acc = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const float2 y = spec[(((size_t)sb * nf + f) * M + m) * n_chan + k];
+    acc += (double)y.x * y.x + (double)y.y * y.y;
+  }
+  int e = 0;
+  if (acc > 0.0) {
+    const double l2 = 0.5 * log2(acc / nf);            // log2 of the RMS magnitude
+    e = (int)lrint((double)target_log2 - l2);
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+  }
+  scale_exp[i] = (int8_t)e;
+}
+
+hipError_t launch_scales(const float2* spec, int n_subbands, int nf, int M, int n_chan,
+                         int target_log2, int8_t* scale_exp, hipStream_t s) {
+  const size_t total = (size_t)n_subbands * M * n_chan;
+  hipLaunchKernelGGL(k_scales, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, spec,
+                     n_subbands, nf, M, n_chan, target_log2, scale_exp);
+  return hipGetLastError();
+}
+
+__device__ inline int bl_of(int i, int j, int M) { return i * M - (i * (i - 1)) / 2 + (j - i); }
+
+// OUT = kOutF16: element = 1 word (Re, Im halves), KC channels = KC words per row,
+//       MFMA 32x32x8, a lane's operand = 4 frames.
+// OUT = kOutF8:  element = 1 half-word (Re, Im bytes), KC channels = KC/2 words per
+//       row, MFMA 32x32x16, a lane's operand = 8 frames.
+// FB frames per LDS stage, CPW channels per wave.
+template <int OUT, int KC, int CPW, int FB>
+__global__ void __launch_bounds__(64 * (KC / CPW))
+    k_xmfma(const DevJob* __restrict__ job, const uint32_t* __restrict__ spec,
+            const int8_t* __restrict__ scale_exp, double2* __restrict__ vacc, int nf) {
+  constexpr int NW = KC / CPW;                       // waves
+  constexpr int NT = 64 * NW;
+  constexpr int RW = OUT == kOutF16 ? KC : KC / 2;   // 32-bit words per (frame, input) row
+  constexpr int FP = FB + 4;                         // LDS frame stride (padding)
+  constexpr int KSTEP = OUT == kOutF16 ? 8 : 16;     // frames per MFMA
+  constexpr int OPF = KSTEP / 2;                     // frames per lane operand
+  extern __shared__ uint32_t lds[];                  // 2 stages of [RW][32][FP] words
+  constexpr int STAGE = RW * 32 * FP;
+  const DevJob& J = *job;
+  const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
+  const int sb = blockIdx.y;
+  const int k0 = blockIdx.x * KC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 31, g = lane >> 5;
+  const size_t row_words = OUT == kOutF16 ? (size_t)n_chan : (size_t)n_chan / 2;   // per spectrum row
+  const uint32_t* src = spec + (size_t)sb * nf * M * row_words + (size_t)k0 * RW / KC;
+
+  // inputs m >= M (and the padding rows) read zeros
+  for (int q = threadIdx.x; q < 2 * STAGE; q += NT) lds[q] = 0u;
+
+  float16_t acc11[CPW], acc22[CPW], acc21[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    acc11[c] = (float16_t){};
+    acc22[c] = (float16_t){};
+    acc21[c] = (float16_t){};
+  }
+
+  // stage loader: FB frames x M inputs x RW words, read along the channel words
+  // (coalesced) and written transposed as [word][input][frame]
+  constexpr int PER = (FB * 32 * RW + NT - 1) / NT;
+  uint32_t pre[PER];
+  auto gload = [&](int f0) {
+    const int nfb = min(FB, nf - f0);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * NT;
+      const int w = q % RW, r = q / RW;            // r = fb * M + input
+      const int fb = r / M, mm = r - fb * M;
+      pre[i] = (r < FB * M && fb < nfb) ? src[((size_t)(f0 + fb) * M + mm) * row_words + w] : 0u;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * NT;
+      const int w = q % RW, r = q / RW;
+      const int fb = r / M, mm = r - fb * M;
+      if (r < FB * M) lds[buf * STAGE + (w * 32 + mm) * FP + fb] = pre[i];
+    }
+  };
+
+  __syncthreads();
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int f0 = 0; f0 < nf; f0 += FB) {
+    const bool more = f0 + FB < nf;
+    if (more) gload(f0 + FB);
+    const uint32_t* st = lds + buf * STAGE;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int ch = wave * CPW + c;                 // channel within the tile
+#pragma unroll
+      for (int ks = 0; ks < FB / KSTEP; ++ks) {
+        const int fbase = ks * KSTEP + g * OPF;
+        if constexpr (OUT == kOutF16) {
+          const uint4 w = *reinterpret_cast<const uint4*>(st + (ch * 32 + m) * FP + fbase);
+          const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+          half4_t re, im;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            re[e] = __builtin_bit_cast(_Float16, (uint16_t)(ww[e] & 0xffffu));
+            im[e] = __builtin_bit_cast(_Float16, (uint16_t)(ww[e] >> 16));
+          }
+          acc11[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(re, re, acc11[c], 0, 0, 0);
+          acc22[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, im, acc22[c], 0, 0, 0);
+          acc21[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, re, acc21[c], 0, 0, 0);
+        } else {
+          // 8 frames of this channel: half-word (ch & 1) of word ch / 2
+          const uint32_t* p = st + ((ch >> 1) * 32 + m) * FP + fbase;
+          const uint4 w0 = *reinterpret_cast<const uint4*>(p);
+          const uint4 w1 = *reinterpret_cast<const uint4*>(p + 4);
+          const uint32_t ww[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+          const int sh = (ch & 1) * 16;
+          uint64_t re = 0, im = 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t h = (ww[e] >> sh) & 0xffffu;
+            re |= (uint64_t)(h & 0xffu) << (8 * e);
+            im |= (uint64_t)(h >> 8) << (8 * e);
+          }
+          acc11[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)re, (long)re, acc11[c], 0, 0, 0);
+          acc22[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)im, (long)im, acc22[c], 0, 0, 0);
+          acc21[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)im, (long)re, acc21[c], 0, 0, 0);
+        }
+      }
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // epilogue: transpose G21 through this wave's own 32 x 33 float scratch
+  float* scr = reinterpret_cast<float*>(lds) + wave * (32 * 33);
+  const int j = lane & 31;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int k = k0 + wave * CPW + c;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 8 * (v >> 2) + 4 * g + (v & 3);
+      scr[i * 33 + j] = acc21[c][v];
+    }
+    __syncthreads();   // uniform: every wave runs CPW epilogue rounds
+    const int ej = j < M ? scale_exp[((size_t)sb * M + j) * n_chan + k] : 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = 8 * (v >> 2) + 4 * g + (v & 3);
+      if (i <= j && j < M) {
+        const int ei = scale_exp[((size_t)sb * M + i) * n_chan + k];
+        const double sc = ldexp(1.0, -(ei + ej));
+        const double re = ((double)acc11[c][v] + (double)acc22[c][v]) * sc;
+        const double im = ((double)acc21[c][v] - (double)scr[j * 33 + i]) * sc;
+        double2* o = vacc + ((size_t)sb * nbl + bl_of(i, j, M)) * n_chan + k;
+        double2 a = *o;
+        a.x += re;
+        a.y += im;
+        *o = a;
+      }
+    }
+    __syncthreads();   // scratch is rewritten by the next round
+  }
+}
+
+template <int OUT, int KC, int CPW, int FB>
+static hipError_t launch_cfg(const DevJob* job, int n_chan, int n_subbands, const void* spec,
+                             const int8_t* scale_exp, double2* vacc, int nf, hipStream_t s) {
+  constexpr int NW = KC / CPW;
+  constexpr int RW = OUT == kOutF16 ? KC : KC / 2;
+  size_t lds = 2 * (size_t)RW * 32 * (FB + 4) * sizeof(uint32_t);
+  const size_t scr = (size_t)NW * 32 * 33 * sizeof(float);
+  if (scr > lds) lds = scr;
+  static bool attr_set = false;
+  if (!attr_set && lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_xmfma<OUT, KC, CPW, FB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  dim3 grid(n_chan / KC, n_subbands);
+  hipLaunchKernelGGL((k_xmfma<OUT, KC, CPW, FB>), grid, dim3(64 * NW), lds, s, job,
+                     static_cast<const uint32_t*>(spec), scale_exp, vacc, nf);
+  return hipGetLastError();
+}
+
+hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_subbands,
+                        const void* spec, const int8_t* scale_exp, double2* vacc,
+                        size_t slot_stride, int nf, hipStream_t s) {
+  (void)slot_stride;
+  if (M > 32 || n_chan < 32) return hipErrorInvalidValue;
+  if (out == kOutF16)
+    return launch_cfg<kOutF16, 16, 2, 16>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
+  if (out == kOutF8)
+    return launch_cfg<kOutF8, 16, 2, 16>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace xc

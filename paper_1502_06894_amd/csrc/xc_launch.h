@@ -19,10 +19,26 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
                          DelayRec* drec, PhaseRec* prec, hipStream_t s);
 // A2-A5: spectra [n_subbands][nf][M][n_chan] for the block's frames.
-// waves: occupancy target of the F kernel (0 = compiler's choice, else 2..4).
+// Spectrum element types written by the F stage.
+constexpr int kOutF32 = 0;   // float2
+constexpr int kOutF16 = 1;   // (Re, Im) FP16, scaled by 2^scale_exp
+constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, saturated at 448
+inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
+
+// waves: occupancy target of the F kernel (0 = compiler's choice, else 3..4; FP32 output only).
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
-                         const PhaseRec* prec, const float2* tw, float2* spec, int nf,
-                         int waves, hipStream_t s);
+                         const PhaseRec* prec, const float2* tw, void* spec,
+                         const int8_t* scale_exp, int nf, int waves, int out, hipStream_t s);
+// Power-of-two exponents per (subband, input, channel) that bring the mean
+// |Y|^2 of the first nf frames (FP32 spectra [n_sb][nf][M][n_chan]) to
+// target_log2 (i.e. RMS 2^target_log2); 0 when a channel has no power.
+hipError_t launch_scales(const float2* spec, int n_subbands, int nf, int M, int n_chan,
+                         int target_log2, int8_t* scale_exp, hipStream_t s);
+// A7: X stage on MFMA for the low-precision spectra (out = kOutF16 or kOutF8),
+// M <= 32; accumulates into the same FP64 slots as the FP32 X stage.
+hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_subbands,
+                        const void* spec, const int8_t* scale_exp, double2* vacc,
+                        size_t slot_stride, int nf, hipStream_t s);
 // Frames one X workgroup accumulates in FP32 before adding to its FP64 slot.
 constexpr int kXmacFramesPerSplit = 256;
 // Accumulator slots a block of nf frames uses (frames split kXmacFramesPerSplit at a time).

@@ -84,6 +84,9 @@ hipError_t timed(xc_ctx* c, int kind, hipStream_t s, Fn&& fn) {
 // Workspace layout of one job.
 struct Layout {
   size_t desc = 0, mask = 0, drec = 0, prec = 0, spec = 0, vacc = 0, wacc = 0, total = 0;
+  size_t sexp = 0;                // int8 scale exponents [n_sb][M][n_chan] (MFMA path)
+  int out = kOutF32;              // spectrum element type written by the F stage
+  int n_scale = 0;                // frames of the scale pre-pass (MFMA path)
   size_t desc_bytes = 0;
   int n_slots = 1;                // FP64 accumulator slots of the X stage
   size_t slot_stride = 0;         // double2 elements per slot
@@ -92,6 +95,9 @@ struct Layout {
 };
 
 constexpr int kMaxBlockFrames = 2048;
+constexpr int kScaleFrames = 64;          // frames that set the MFMA path's channel scales
+constexpr int kF16TargetLog2 = 10;        // FP16: scaled RMS 2^10 (max 65504)
+constexpr int kF8TargetLog2 = 5;          // e4m3: scaled RMS 2^5 (max 448)
 constexpr int kDefaultBlockFrames = 2048;
 
 int block_frames(const xc_setup* s, const xc_ctx* c) {
@@ -126,8 +132,11 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
       return fail(c, XC_E_INVAL, "stream_map[%d]=%d outside 0..%d", i, s->stream_map[i], C - 1);
   if (!(s->fs_hz > 0.0) || !isfinite(s->fs_hz)) return fail(c, XC_E_INVAL, "fs_hz invalid");
   if (s->n_frames < 1) return fail(c, XC_E_INVAL, "n_frames=%lld", (long long)s->n_frames);
-  if (s->precision != XC_FP32)
-    return fail(c, XC_E_INVAL, "precision %d not available on this path", s->precision);
+  if (s->precision != XC_FP32 && s->precision != XC_FP16_MFMA && s->precision != XC_FP8_MFMA)
+    return fail(c, XC_E_INVAL, "precision %d unknown", s->precision);
+  if (s->precision != XC_FP32 && s->n_stations * s->n_pols > 32)
+    return fail(c, XC_E_INVAL, "MFMA X stage takes at most 32 inputs per subband (M=%d)",
+                s->n_stations * s->n_pols);
   if (s->frames_per_block < 0 || s->frames_per_block > kMaxBlockFrames)
     return fail(c, XC_E_INVAL, "frames_per_block=%d outside 0..%d", s->frames_per_block,
                 kMaxBlockFrames);
@@ -172,8 +181,17 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_ctx* c) {
   off += align_up((size_t)S * L.T * sizeof(DelayRec));
   L.prec = off;
   off += align_up((size_t)S * nsb * L.T * sizeof(PhaseRec));
+  L.out = s->precision == XC_FP16_MFMA ? kOutF16 : s->precision == XC_FP8_MFMA ? kOutF8 : kOutF32;
   L.spec = off;
-  off += align_up((size_t)nsb * L.T * M * s->n_chan * sizeof(float2));
+  size_t spec_bytes = (size_t)nsb * L.T * M * s->n_chan * out_elem_bytes(L.out);
+  if (L.out != kOutF32) {
+    L.n_scale = L.T < kScaleFrames ? L.T : kScaleFrames;
+    const size_t pre = (size_t)nsb * L.n_scale * M * s->n_chan * sizeof(float2);
+    if (pre > spec_bytes) spec_bytes = pre;
+  }
+  off += align_up(spec_bytes);
+  L.sexp = off;
+  if (L.out != kOutF32) off += align_up((size_t)nsb * M * s->n_chan);
   L.n_slots = xmac_splits(L.T);
   L.slot_stride = (size_t)nsb * nbl * s->n_chan;
   L.vacc = off;
@@ -381,6 +399,20 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
                        stream);
   });
   if (e != hipSuccess) return hip_fail(c, e, "zero");
+  int8_t* sexp = reinterpret_cast<int8_t*>(ws + L.sexp);
+  if (L.out != kOutF32) {
+    // channel scales from the first frames' FP32 spectra
+    e = launch_delays(dj, S, nsb, 0, L.n_scale, drec, prec, stream);
+    if (e == hipSuccess)
+      e = timed(c, XC_K_FSTAGE, stream, [&] {
+        return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nullptr, L.n_scale, 0, kOutF32,
+                             stream);
+      });
+    if (e == hipSuccess)
+      e = launch_scales(spec, nsb, L.n_scale, M, s->n_chan,
+                        L.out == kOutF16 ? kF16TargetLog2 : kF8TargetLog2, sexp, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "scales");
+  }
   for (int64_t f0 = 0; f0 < s->n_frames; f0 += L.T) {
     const int nf = (int)((s->n_frames - f0) < L.T ? (s->n_frames - f0) : L.T);
     e = timed(c, XC_K_DELAYS, stream, [&] {
@@ -388,17 +420,23 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
       return r == hipSuccess ? launch_weights(drec, S, nf, wacc, stream) : r;
     });
     if (e != hipSuccess) return hip_fail(c, e, "delays");
-    e = timed(c, XC_K_FSTAGE, stream,
-              [&] {
-                return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nf,
-                                     c->tune.fstage_waves_per_simd, stream);
-              });
-    if (e != hipSuccess) return hip_fail(c, e, "fstage");
-    e = timed(c, XC_K_XMAC, stream, [&] {
-      return launch_xmac(dj, M, s->n_chan, nsb, spec, vacc, L.slot_stride, nf,
-                         c->tune.xmac_frames_per_stage, c->tune.xmac_channels_per_wg,
-                         c->tune.xmac_tiles_per_wg, stream);
+    e = timed(c, XC_K_FSTAGE, stream, [&] {
+      return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, sexp, nf,
+                           c->tune.fstage_waves_per_simd, L.out, stream);
     });
+    if (e != hipSuccess) return hip_fail(c, e, "fstage");
+    if (L.out == kOutF32) {
+      e = timed(c, XC_K_XMAC, stream, [&] {
+        return launch_xmac(dj, M, s->n_chan, nsb, spec, vacc, L.slot_stride, nf,
+                           c->tune.xmac_frames_per_stage, c->tune.xmac_channels_per_wg,
+                           c->tune.xmac_tiles_per_wg, stream);
+      });
+    } else {
+      e = timed(c, XC_K_XMFMA, stream, [&] {
+        return launch_xmfma(dj, L.out, M, s->n_chan, nsb, spec, sexp, vacc, L.slot_stride, nf,
+                            stream);
+      });
+    }
     if (e != hipSuccess) return hip_fail(c, e, "xmac");
   }
   e = timed(c, XC_K_FINALISE, stream, [&] {
@@ -544,8 +582,8 @@ int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t
   PhaseRec* prec = reinterpret_cast<PhaseRec*>(ws + L.prec);
   hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, stream);
   if (e == hipSuccess)
-    e = launch_fstage(2 * s->n_chan, dj, s->n_stations, drec, prec, c->d_tw,
-                      static_cast<float2*>(spectra), n, c->tune.fstage_waves_per_simd, stream);
+    e = launch_fstage(2 * s->n_chan, dj, s->n_stations, drec, prec, c->d_tw, spectra, nullptr, n,
+                      c->tune.fstage_waves_per_simd, kOutF32, stream);
   return e == hipSuccess ? XC_OK : hip_fail(c, e, "debug_spectra");
 }
 

@@ -1,0 +1,79 @@
+"""GPU: the MFMA X stage with FP16 / FP8 (e4m3) spectra against the FP64 oracle.
+
+Each spectrum component is rounded once (after a power-of-two scale that
+cannot overflow for these data), so |dY| <= u |Y| with u = 2^-11 (FP16) or
+2^-4 (e4m3), and every product Y_i conj(Y_j) is off by at most
+(2u + u^2)|Y_i||Y_j|.  Averaged over frames and bounded by Cauchy-Schwarz:
+    |dV_ij[k]| <= (2u + u^2) sqrt(A_i[k] A_j[k])
+with A the oracle's autocorrelations.  The test asserts that bound (10 %
+slack for FP32 accumulation and the FP32 F stage) per baseline, subband and
+channel, and prints the per-baseline error table.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fx
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+U = {"fp16": 2.0 ** -11, "fp8": 2.0 ** -4}
+
+
+@pytest.fixture(scope="module")
+def xc():
+    from paper_1502_06894_amd import xcorr
+    return xcorr
+
+
+@pytest.fixture(scope="module")
+def corr(xc):
+    return xc.Correlator(0)
+
+
+def _norm_err(vis, V, job):
+    M = job.M
+    worst = 0.0
+    rows = []
+    for sb in range(job.n_subbands):
+        for i in range(M):
+            for j in range(i, M):
+                bl = fx.baseline_index(i, j, M)
+                Ai = V[sb, fx.baseline_index(i, i, M)].real
+                Aj = V[sb, fx.baseline_index(j, j, M)].real
+                d = np.abs(vis[sb, bl] - V[sb, bl]) / np.sqrt(Ai * Aj)
+                rel = np.linalg.norm(vis[sb, bl] - V[sb, bl]) / np.linalg.norm(V[sb, bl])
+                worst = max(worst, float(d.max()))
+                rows.append((sb, i, j, float(d.max()), float(rel)))
+    return worst, rows
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp8"])
+@pytest.mark.parametrize("kw", [
+    dict(n_stations=32, n_subbands=2, n_pols=1, n_chan=512, C=4, n_frames=96, realistic=False),
+    dict(n_stations=6, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=75),
+], ids=["m32", "dualpol"])
+def test_mfma_precision_bound(xc, corr, prec, kw):
+    job = configs.small_job(**kw, seed=17)
+    V, W = fx.correlate(job, threads=8)
+    xc.job_to_device(job)
+    vis, w = corr.correlate(job, precision=xc.PRECISIONS[prec], frames_per_block=64)
+    torch.cuda.synchronize()
+    vis, w = vis.cpu().numpy(), w.cpu().numpy()
+    assert np.array_equal(w, W.astype(np.float32))
+    worst, rows = _norm_err(vis, V, job)
+    u = U[prec]
+    bound = 1.1 * (2 * u + u * u)
+    rel = np.array([r[4] for r in rows])
+    print(f"\n{prec} {job.M} inputs: max |dV|/sqrt(AiAj) = {worst:.3e} (bound {bound:.3e}); "
+          f"per-baseline relative L2: median {np.median(rel):.3e}, max {rel.max():.3e}")
+    assert worst <= bound
+
+
+def test_mfma_rejects_more_than_32_inputs(xc, corr):
+    job = configs.small_job(n_stations=17, n_subbands=1, n_pols=2, n_chan=128, C=2, n_frames=4)
+    xc.job_to_device(job)
+    with pytest.raises(xc.XcError) as e:
+        corr.correlate(job, precision=xc.XC_FP16_MFMA)
+    assert e.value.code == xc.XC_E_INVAL
