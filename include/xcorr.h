@@ -179,6 +179,78 @@ typedef struct {
 int xc_set_tuning(xc_ctx* ctx, const xc_tuning* t);
 int xc_get_tuning(const xc_ctx* ctx, xc_tuning* t);
 
+/* ---------------------------------------------------------------- batches */
+/* A batch runs many sub-integrations of uneven shapes as one unit: jobs are
+ * spread longest-first over n_lanes concurrent HIP streams ("lanes"), each
+ * lane with its own workspace arena, so small jobs overlap on the device and
+ * the GPU stays full; results are identical to running each job alone.  With
+ * XC_BATCH_GRAPH the launches are captured once as a hipGraph and a later call
+ * with an identical batch replays the graph (one launch). */
+typedef struct {
+  xc_setup setup;
+  const xc_station* st;        /* host [setup.n_stations] */
+  xc_output out;
+} xc_job;
+
+#define XC_BATCH_GRAPH 1
+
+/* Device workspace a batch needs (0 if a job is invalid). */
+size_t xc_batch_workspace_bytes(xc_ctx* ctx, const xc_job* jobs, int32_t n_jobs,
+                                int32_t n_lanes);
+/* Correlate jobs[0..n_jobs) (1 <= n_lanes <= 16).  Async on `stream`: all
+ * results are complete when the stream reaches this point.  Error codes as
+ * for xc_correlate_subint; the message names the failing job. */
+int xc_correlate_batch(xc_ctx* ctx, const xc_job* jobs, int32_t n_jobs, int32_t n_lanes,
+                       int32_t flags, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- serving */
+/* A server admits correlation requests continuously: each request needs a
+ * slot (one of max_slots concurrent HIP streams) and its workspace footprint
+ * from a device pool of hbm_budget_bytes allocated at creation; requests that
+ * arrive while others run start as soon as a slot and memory are free, and
+ * their work overlaps on the device.  Admission is first-in first-out, except
+ * that a later request may start ahead of one that does not fit yet (at most
+ * 8 times, then the earlier one blocks admission until it fits).  Results do
+ * not depend on what else runs.  Station recordings and outputs stay
+ * caller-owned device memory and must stay valid until the request is done;
+ * the job description (setup, stations, polynomials) is copied at submit. */
+typedef struct xc_server xc_server;
+
+typedef struct {
+  double p50_ms, p99_ms, mean_ms;  /* latency: submit -> completion seen by the server */
+  int64_t completed;               /* finished with XC_OK */
+  int64_t failed, cancelled;
+  int64_t queued, running;         /* now */
+  double station_samples_per_s;    /* completed work / (last completion - first submit) */
+} xc_server_stats;
+
+int  xc_server_create(xc_server** out, int hip_device, size_t hbm_budget_bytes,
+                      int32_t max_slots);
+/* XC_E_NOMEM if the job's footprint exceeds the whole budget; XC_E_INVAL or
+ * XC_E_RANGE for an invalid job; otherwise queues it and sets *ticket. */
+int  xc_server_submit(xc_server* srv, const xc_job* job, uint64_t* ticket);
+/* *done = 1 once the request finished; returns its result code then. */
+int  xc_server_poll(xc_server* srv, uint64_t ticket, int32_t* done);
+/* Block until done (returns its result code) or XC_E_TIMEOUT after timeout_ms (< 0: no limit). */
+int  xc_server_wait(xc_server* srv, uint64_t ticket, int32_t timeout_ms);
+/* A queued request is dropped; a running one completes on the device but
+ * reports XC_E_CANCELLED.  XC_E_INVAL for an unknown or finished ticket. */
+int  xc_server_cancel(xc_server* srv, uint64_t ticket);
+int  xc_server_get_stats(xc_server* srv, xc_server_stats* out);
+const char* xc_server_last_error(xc_server* srv);
+/* Cancels queued requests, waits for running ones, frees the pool. */
+void xc_server_destroy(xc_server* srv);
+
+/* ---------------------------------------------------------------- autotuner */
+/* Time candidate launch shapes (frames per block; X-stage stage depth and
+ * channel tile) on this job (its first frames) and remember the fastest for
+ * every job of the same shape (FFT length, inputs, subbands, recorded
+ * streams, precision) on this context.  Runs on `stream` and synchronises.
+ * out/workspace as for xc_correlate_subint; candidates whose workspace does
+ * not fit ws_bytes are skipped.  best (host) may be NULL. */
+int xc_autotune(xc_ctx* ctx, const xc_setup* setup, const xc_station* st, const xc_output* out,
+                void* workspace, size_t ws_bytes, void* stream, xc_tuning* best);
+
 /* ---------------------------------------------------------------- kernel timing */
 /* Kernel kinds for xc_profile_end. */
 #define XC_K_INGEST    0

@@ -1,0 +1,117 @@
+// Host runtime shared by the C-ABI entry points: context, validation,
+// per-job workspace arena layout, descriptor building and the launch sequence
+// of one job.  Used by xcorr.hip (single jobs, taps), batch.hip (batches,
+// autotuner) and server.hip (continuous-batching server).
+#pragma once
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/xcorr.h"
+#include "xc_launch.h"
+
+namespace xc {
+
+constexpr int kSlots = 8;                 // pinned descriptor staging slots per context
+constexpr size_t kSlotBytes = 256 * 1024;
+constexpr size_t kAlign = 256;
+constexpr int kMaxBlockFrames = 2048;
+constexpr int kDefaultBlockFrames = 2048;
+constexpr int kScaleFrames = 64;          // frames that set the MFMA path's channel scales
+constexpr int kF16TargetLog2 = 10;        // FP16: scaled RMS 2^10 (max 65504)
+constexpr int kF8TargetLog2 = 5;          // e4m3: scaled RMS 2^5 (max 448)
+constexpr int kMaxLanes = 16;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Timed {
+  int kind;
+  hipEvent_t a, b;
+};
+
+// Shape key of the autotune cache: FFT length, inputs, subbands, recorded streams, precision.
+using ShapeKey = std::tuple<int, int, int, int, int>;
+
+}  // namespace xc
+
+struct xc_ctx {
+  int device = 0;
+  xc_tuning tune = {0, 0, 0, 0, 0};          // explicit overrides (0 = auto)
+  std::map<xc::ShapeKey, xc_tuning> tuned;   // autotuned shapes
+  bool profiling = false;
+  bool capturing = false;                    // inside a graph capture: no profiling events
+  std::vector<xc::Timed> prof;
+  size_t prof_used = 0;
+  float2* d_tw = nullptr;                    // FFT twiddles, kTwiddleN entries
+  unsigned char* h_stage = nullptr;          // kSlots x kSlotBytes pinned
+  hipEvent_t ev[xc::kSlots] = {};
+  int next_slot = 0;
+  std::vector<hipStream_t> lanes;            // batch lanes (default priority)
+  std::vector<hipEvent_t> lane_ev;           // join events, one per lane
+  hipEvent_t fork_ev = nullptr;
+  struct GraphEntry {
+    uint64_t key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;            // captured batches, most recent last
+  unsigned char* h_batch = nullptr;          // pinned descriptor blob of the last batch
+  size_t h_batch_bytes = 0;
+  hipEvent_t batch_ev = nullptr;             // the blob's upload has completed
+  std::string last_error;
+};
+
+namespace xc {
+
+int fail(xc_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int hip_fail(xc_ctx* c, hipError_t e, const char* what);
+
+// Run a launcher, bracketed by an event pair when profiling is on.
+template <class Fn>
+hipError_t timed(xc_ctx* c, int kind, hipStream_t s, Fn&& fn) {
+  if (!c->profiling || c->capturing || c->prof_used >= c->prof.size()) return fn();
+  Timed& t = c->prof[c->prof_used++];
+  t.kind = kind;
+  hipError_t e = hipEventRecord(t.a, s);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  return hipEventRecord(t.b, s);
+}
+
+// Per-job arena: everything a job needs besides its descriptor.
+struct Layout {
+  size_t desc_bytes = 0;          // descriptor size (stored outside the arena)
+  size_t mask = 0, drec = 0, prec = 0, spec = 0, sexp = 0, vacc = 0, wacc = 0, total = 0;
+  std::vector<size_t> mask_off;   // per station, SIZE_MAX if the caller supplies frame_ok
+  int T = 0;                      // frames per block
+  int out = kOutF32;              // spectrum element type written by the F stage
+  int n_scale = 0;                // frames of the scale pre-pass (MFMA path)
+  int n_slots = 1;                // FP64 accumulator slots of the X stage
+  size_t slot_stride = 0;         // double2 elements per slot
+};
+
+ShapeKey shape_key(const xc_setup* s);
+// Launch shape for a job: explicit context overrides, else the autotuned
+// entry for the job's shape, else built-in defaults (zeros).
+xc_tuning effective_tuning(const xc_ctx* c, const xc_setup* s);
+int validate(xc_ctx* c, const xc_setup* s, const xc_station* st);
+Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu);
+// Descriptor for device address `dev_desc`; stations' frame_ok default to the arena masks.
+void build_desc(const xc_setup* s, const xc_station* st, const Layout& L,
+                const unsigned char* dev_desc, const unsigned char* arena, unsigned char* h);
+// Stage one descriptor through a pinned ring slot and copy it to dev_desc.
+int upload_desc(xc_ctx* c, const xc_setup* s, const xc_station* st, const Layout& L,
+                unsigned char* dev_desc, const unsigned char* arena, hipStream_t stream);
+// Enqueue every kernel of one job (ingest .. finalise) on `stream`.
+int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
+                const DevJob* dj, unsigned char* arena, const Layout& L, const xc_tuning& tu,
+                hipStream_t stream);
+int ensure_lanes(xc_ctx* c, int n);
+
+}  // namespace xc

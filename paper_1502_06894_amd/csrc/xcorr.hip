@@ -1,49 +1,11 @@
 // C-ABI runtime: context, setup validation, workspace layout, descriptor
 // upload and launch sequencing of the correlation path.
 #include <math.h>
-#include <stdarg.h>
-#include <stdio.h>
-#include <string.h>
 
-#include <string>
-#include <vector>
+#include "xc_runtime.h"
 
-#include "../../include/xcorr.h"
-#include "xc_launch.h"
+namespace xc {
 
-using namespace xc;
-
-namespace {
-
-constexpr int kSlots = 8;
-constexpr size_t kSlotBytes = 256 * 1024;
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-}  // namespace
-
-struct Timed {
-  int kind;
-  hipEvent_t a, b;
-};
-
-struct xc_ctx {
-  int device = 0;
-  xc_tuning tune = {0, 0, 0, 0, 0};
-  bool profiling = false;
-  std::vector<Timed> prof;        // event pairs, reused across profile sessions
-  size_t prof_used = 0;
-  float2* d_tw = nullptr;                 // kTwiddleN entries
-  unsigned char* h_stage = nullptr;       // kSlots x kSlotBytes pinned
-  hipEvent_t ev[kSlots] = {};
-  int next_slot = 0;
-  std::string last_error;
-};
-
-namespace {
-
-int fail(xc_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int fail(xc_ctx* c, int code, const char* fmt, ...) {
   if (c) {
     char buf[512];
@@ -60,6 +22,8 @@ int hip_fail(xc_ctx* c, hipError_t e, const char* what) {
   return fail(c, XC_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+namespace {
+
 bool pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 int ilog2(int x) {
@@ -68,42 +32,31 @@ int ilog2(int x) {
   return l;
 }
 
-// Run a launcher, bracketed by an event pair when profiling is on.
-template <class Fn>
-hipError_t timed(xc_ctx* c, int kind, hipStream_t s, Fn&& fn) {
-  if (!c->profiling || c->prof_used >= c->prof.size()) return fn();
-  Timed& t = c->prof[c->prof_used++];
-  t.kind = kind;
-  hipError_t e = hipEventRecord(t.a, s);
-  if (e != hipSuccess) return e;
-  e = fn();
-  if (e != hipSuccess) return e;
-  return hipEventRecord(t.b, s);
+}  // namespace
+
+ShapeKey shape_key(const xc_setup* s) {
+  return ShapeKey(2 * s->n_chan, s->n_stations * s->n_pols, s->n_subbands,
+                  s->n_streams_recorded, s->precision);
 }
 
-// Workspace layout of one job.
-struct Layout {
-  size_t desc = 0, mask = 0, drec = 0, prec = 0, spec = 0, vacc = 0, wacc = 0, total = 0;
-  size_t sexp = 0;                // int8 scale exponents [n_sb][M][n_chan] (MFMA path)
-  int out = kOutF32;              // spectrum element type written by the F stage
-  int n_scale = 0;                // frames of the scale pre-pass (MFMA path)
-  size_t desc_bytes = 0;
-  int n_slots = 1;                // FP64 accumulator slots of the X stage
-  size_t slot_stride = 0;         // double2 elements per slot
-  std::vector<size_t> mask_off;   // per station, SIZE_MAX if caller supplies frame_ok
-  int T = 0;                      // frames per block
-};
+xc_tuning effective_tuning(const xc_ctx* c, const xc_setup* s) {
+  xc_tuning t = {0, 0, 0, 0, 0};
+  if (!c) return t;
+  auto it = c->tuned.find(shape_key(s));
+  if (it != c->tuned.end()) t = it->second;
+  const xc_tuning& o = c->tune;
+  if (o.fstage_waves_per_simd) t.fstage_waves_per_simd = o.fstage_waves_per_simd;
+  if (o.xmac_frames_per_stage) t.xmac_frames_per_stage = o.xmac_frames_per_stage;
+  if (o.xmac_channels_per_wg) t.xmac_channels_per_wg = o.xmac_channels_per_wg;
+  if (o.frames_per_block) t.frames_per_block = o.frames_per_block;
+  if (o.xmac_tiles_per_wg) t.xmac_tiles_per_wg = o.xmac_tiles_per_wg;
+  return t;
+}
 
-constexpr int kMaxBlockFrames = 2048;
-constexpr int kScaleFrames = 64;          // frames that set the MFMA path's channel scales
-constexpr int kF16TargetLog2 = 10;        // FP16: scaled RMS 2^10 (max 65504)
-constexpr int kF8TargetLog2 = 5;          // e4m3: scaled RMS 2^5 (max 448)
-constexpr int kDefaultBlockFrames = 2048;
-
-int block_frames(const xc_setup* s, const xc_ctx* c) {
+static int block_frames(const xc_setup* s, const xc_tuning& tu) {
   int64_t T = s->frames_per_block > 0 ? s->frames_per_block
-              : (c && c->tune.frames_per_block > 0) ? c->tune.frames_per_block
-                                                     : kDefaultBlockFrames;
+              : tu.frames_per_block > 0 ? tu.frames_per_block
+                                        : kDefaultBlockFrames;
   if (T > s->n_frames) T = s->n_frames;
   return (int)T;
 }
@@ -160,16 +113,14 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
   return XC_OK;
 }
 
-Layout layout_of(const xc_setup* s, const xc_station* st, const xc_ctx* c) {
+Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu) {
   Layout L;
   const int S = s->n_stations, nsb = s->n_subbands, M = S * s->n_pols;
   const size_t nbl = (size_t)M * (M + 1) / 2;
-  L.T = block_frames(s, c);
+  L.T = block_frames(s, tu);
   L.desc_bytes = sizeof(DevJob) + (size_t)S * sizeof(DevStation) +
                  (size_t)S * nsb * (kMaxPolyDeg + 1) * sizeof(double);
   size_t off = 0;
-  L.desc = off;
-  off += align_up(L.desc_bytes);
   L.mask = off;
   L.mask_off.assign(S, SIZE_MAX);
   for (int i = 0; i < S; ++i)
@@ -192,7 +143,7 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_ctx* c) {
   off += align_up(spec_bytes);
   L.sexp = off;
   if (L.out != kOutF32) off += align_up((size_t)nsb * M * s->n_chan);
-  L.n_slots = xmac_splits(L.T);
+  L.n_slots = L.out == kOutF32 ? xmac_splits(L.T) : 1;
   L.slot_stride = (size_t)nsb * nbl * s->n_chan;
   L.vacc = off;
   off += (size_t)L.n_slots * L.slot_stride * sizeof(double2);   // wacc follows directly
@@ -203,8 +154,8 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_ctx* c) {
 }
 
 // Build the job descriptor for device address `dev` into host memory `h`.
-void build_desc(const xc_setup* s, const xc_station* st, const Layout& L, unsigned char* ws,
-                unsigned char* h) {
+void build_desc(const xc_setup* s, const xc_station* st, const Layout& L,
+                const unsigned char* dev_desc, const unsigned char* arena, unsigned char* h) {
   const int S = s->n_stations, nsb = s->n_subbands;
   DevJob* J = reinterpret_cast<DevJob*>(h);
   memset(h, 0, L.desc_bytes);
@@ -225,7 +176,7 @@ void build_desc(const xc_setup* s, const xc_station* st, const Layout& L, unsign
   J->n_frames = s->n_frames;
   for (int i = 0; i < J->n_inputs; ++i) J->stream_map[i] = s->stream_map[i];
   for (int b = 0; b < nsb; ++b) J->lo_hz[b] = s->lo_hz[b];
-  unsigned char* dev = ws + L.desc;
+  const unsigned char* dev = dev_desc;
   DevStation* hs = reinterpret_cast<DevStation*>(h + sizeof(DevJob));
   double* hp = reinterpret_cast<double*>(h + sizeof(DevJob) + (size_t)S * sizeof(DevStation));
   J->st = reinterpret_cast<const DevStation*>(dev + sizeof(DevJob));
@@ -235,7 +186,7 @@ void build_desc(const xc_setup* s, const xc_station* st, const Layout& L, unsign
     DevStation& d = hs[i];
     d.words = static_cast<const uint32_t*>(st[i].frames);
     d.frame_ok = st[i].frame_ok ? st[i].frame_ok
-                                : reinterpret_cast<const uint8_t*>(ws + L.mask + L.mask_off[i]);
+                                : reinterpret_cast<const uint8_t*>(arena + L.mask + L.mask_off[i]);
     d.n_frames_m5b = st[i].n_frames_m5b;
     d.first_sample = st[i].first_sample;
     d.poly_deg = st[i].poly_deg;
@@ -250,49 +201,155 @@ void build_desc(const xc_setup* s, const xc_station* st, const Layout& L, unsign
   }
 }
 
-// Stage the descriptor through a pinned slot and copy it into the workspace.
 int upload_desc(xc_ctx* c, const xc_setup* s, const xc_station* st, const Layout& L,
-                unsigned char* ws, hipStream_t stream) {
+                unsigned char* dev_desc, const unsigned char* arena, hipStream_t stream) {
   if (L.desc_bytes > kSlotBytes) return fail(c, XC_E_INVAL, "descriptor too large");
   const int k = c->next_slot;
   c->next_slot = (k + 1) % kSlots;
   hipError_t e = hipEventSynchronize(c->ev[k]);
   if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
   unsigned char* h = c->h_stage + (size_t)k * kSlotBytes;
-  build_desc(s, st, L, ws, h);
-  e = hipMemcpyAsync(ws + L.desc, h, L.desc_bytes, hipMemcpyHostToDevice, stream);
+  build_desc(s, st, L, dev_desc, arena, h);
+  e = hipMemcpyAsync(dev_desc, h, L.desc_bytes, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return hip_fail(c, e, "descriptor upload");
   e = hipEventRecord(c->ev[k], stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
   return XC_OK;
 }
 
-// Common prologue: validate, lay out, check workspace, upload, ingest.
+int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
+                const DevJob* dj, unsigned char* arena, const Layout& L, const xc_tuning& tu,
+                hipStream_t stream) {
+  DelayRec* drec = reinterpret_cast<DelayRec*>(arena + L.drec);
+  PhaseRec* prec = reinterpret_cast<PhaseRec*>(arena + L.prec);
+  void* spec = arena + L.spec;
+  double2* vacc = reinterpret_cast<double2*>(arena + L.vacc);
+  double* wacc = reinterpret_cast<double*>(arena + L.wacc);
+  int8_t* sexp = reinterpret_cast<int8_t*>(arena + L.sexp);
+  const int S = s->n_stations, nsb = s->n_subbands, M = S * s->n_pols;
+  const int N = 2 * s->n_chan;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < S && e == hipSuccess; ++i)
+    if (!st[i].frame_ok)
+      e = timed(c, XC_K_INGEST, stream, [&] {
+        return launch_ingest(static_cast<const uint32_t*>(st[i].frames), st[i].n_frames_m5b,
+                             reinterpret_cast<uint8_t*>(arena + L.mask + L.mask_off[i]), stream);
+      });
+  if (e != hipSuccess) return hip_fail(c, e, "ingest");
+  e = timed(c, XC_K_ZERO, stream, [&] {
+    return launch_zero(reinterpret_cast<double*>(vacc), (L.total - L.vacc) / sizeof(double),
+                       stream);
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "zero");
+  if (L.out != kOutF32) {
+    // channel scales from the first frames' FP32 spectra
+    e = launch_delays(dj, S, nsb, 0, L.n_scale, drec, prec, stream);
+    if (e == hipSuccess)
+      e = timed(c, XC_K_FSTAGE, stream, [&] {
+        return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nullptr, L.n_scale, 0, kOutF32,
+                             stream);
+      });
+    if (e == hipSuccess)
+      e = launch_scales(static_cast<const float2*>(spec), nsb, L.n_scale, M, s->n_chan,
+                        L.out == kOutF16 ? kF16TargetLog2 : kF8TargetLog2, sexp, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "scales");
+  }
+  for (int64_t f0 = 0; f0 < s->n_frames; f0 += L.T) {
+    const int nf = (int)((s->n_frames - f0) < L.T ? (s->n_frames - f0) : L.T);
+    e = timed(c, XC_K_DELAYS, stream, [&] {
+      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec, prec, stream);
+      return r == hipSuccess ? launch_weights(drec, S, nf, wacc, stream) : r;
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "delays");
+    e = timed(c, XC_K_FSTAGE, stream, [&] {
+      return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, sexp, nf,
+                           tu.fstage_waves_per_simd, L.out, stream);
+    });
+    if (e != hipSuccess) return hip_fail(c, e, "fstage");
+    if (L.out == kOutF32) {
+      e = timed(c, XC_K_XMAC, stream, [&] {
+        return launch_xmac(dj, M, s->n_chan, nsb, static_cast<const float2*>(spec), vacc,
+                           L.slot_stride, nf, tu.xmac_frames_per_stage, tu.xmac_channels_per_wg,
+                           tu.xmac_tiles_per_wg, stream);
+      });
+    } else {
+      e = timed(c, XC_K_XMFMA, stream, [&] {
+        return launch_xmfma(dj, L.out, M, s->n_chan, nsb, spec, sexp, vacc, L.slot_stride, nf,
+                            stream);
+      });
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "xmac");
+  }
+  e = timed(c, XC_K_FINALISE, stream, [&] {
+    return launch_finalise(vacc, L.n_slots, L.slot_stride, wacc, S, s->n_pols,
+                           static_cast<float2*>(out->vis), out->weight, nsb, M, s->n_chan,
+                           stream);
+  });
+  if (e != hipSuccess) return hip_fail(c, e, "finalise");
+  return XC_OK;
+}
+
+int ensure_lanes(xc_ctx* c, int n) {
+  hipError_t e = hipSuccess;
+  while (e == hipSuccess && (int)c->lanes.size() < n) {
+    hipStream_t st;
+    hipEvent_t ev;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);   // default priority
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) {
+      c->lanes.push_back(st);
+      c->lane_ev.push_back(ev);
+    }
+  }
+  if (e == hipSuccess && !c->fork_ev) e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming);
+  return e == hipSuccess ? XC_OK : hip_fail(c, e, "lanes");
+}
+
+namespace {
+
+// Single-job workspace: [descriptor][arena].
+struct Prepared {
+  Layout L;
+  xc_tuning tu;
+  unsigned char* desc;
+  unsigned char* arena;
+};
+
 int prepare(xc_ctx* c, const xc_setup* s, const xc_station* st, void* workspace,
-            size_t ws_bytes, hipStream_t stream, Layout& L) {
+            size_t ws_bytes, hipStream_t stream, Prepared& p) {
   if (!c) return XC_E_INVAL;
   int rc = validate(c, s, st);
   if (rc != XC_OK) return rc;
-  L = layout_of(s, st, c);
-  if (!workspace || ws_bytes < L.total)
-    return fail(c, XC_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
+  p.tu = effective_tuning(c, s);
+  p.L = layout_of(s, st, p.tu);
+  const size_t need = align_up(p.L.desc_bytes) + p.L.total;
+  if (!workspace || ws_bytes < need)
+    return fail(c, XC_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
-  unsigned char* ws = static_cast<unsigned char*>(workspace);
-  rc = upload_desc(c, s, st, L, ws, stream);
-  if (rc != XC_OK) return rc;
+  p.desc = static_cast<unsigned char*>(workspace);
+  p.arena = p.desc + align_up(p.L.desc_bytes);
+  return upload_desc(c, s, st, p.L, p.desc, p.arena, stream);
+}
+
+// Ingest masks of stations without a caller-supplied frame_ok (taps only; the
+// correlation path does this inside enqueue_job).
+int ingest_missing(xc_ctx* c, const xc_setup* s, const xc_station* st, const Prepared& p,
+                   hipStream_t stream) {
   for (int i = 0; i < s->n_stations; ++i)
     if (!st[i].frame_ok) {
-      e = timed(c, XC_K_INGEST, stream, [&] {
-        return launch_ingest(static_cast<const uint32_t*>(st[i].frames), st[i].n_frames_m5b,
-                             reinterpret_cast<uint8_t*>(ws + L.mask + L.mask_off[i]), stream);
-      });
+      hipError_t e =
+          launch_ingest(static_cast<const uint32_t*>(st[i].frames), st[i].n_frames_m5b,
+                        reinterpret_cast<uint8_t*>(p.arena + p.L.mask + p.L.mask_off[i]), stream);
       if (e != hipSuccess) return hip_fail(c, e, "ingest");
     }
   return XC_OK;
 }
 
 }  // namespace
+}  // namespace xc
+
+using namespace xc;
 
 extern "C" {
 
@@ -341,19 +398,31 @@ int xc_create(xc_ctx** out, int hip_device) {
 
 void xc_destroy(xc_ctx* c) {
   if (!c) return;
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   for (Timed& t : c->prof) {
-    hipEventSynchronize(t.b);
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventSynchronize(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
   for (int k = 0; k < kSlots; ++k)
     if (c->ev[k]) {
-      hipEventSynchronize(c->ev[k]);
-      hipEventDestroy(c->ev[k]);
+      (void)hipEventSynchronize(c->ev[k]);
+      (void)hipEventDestroy(c->ev[k]);
     }
-  if (c->h_stage) hipHostFree(c->h_stage);
-  if (c->d_tw) hipFree(c->d_tw);
+  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  for (size_t i = 0; i < c->lanes.size(); ++i) {
+    (void)hipStreamSynchronize(c->lanes[i]);
+    (void)hipStreamDestroy(c->lanes[i]);
+    (void)hipEventDestroy(c->lane_ev[i]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->batch_ev) {
+    (void)hipEventSynchronize(c->batch_ev);
+    (void)hipEventDestroy(c->batch_ev);
+  }
+  if (c->h_batch) (void)hipHostFree(c->h_batch);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  if (c->d_tw) (void)hipFree(c->d_tw);
   delete c;
 }
 
@@ -375,77 +444,19 @@ int xc_validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
 
 size_t xc_workspace_bytes(const xc_ctx* c, const xc_setup* s, const xc_station* st) {
   if (validate(const_cast<xc_ctx*>(c), s, st) != XC_OK) return 0;
-  return layout_of(s, st, c).total;
+  const Layout L = layout_of(s, st, effective_tuning(c, s));
+  return align_up(L.desc_bytes) + L.total;
 }
 
 int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
                         void* workspace, size_t ws_bytes, void* stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  Layout L;
-  int rc = prepare(c, s, st, workspace, ws_bytes, stream, L);
+  if (c && (!out || !out->vis || !out->weight)) return fail(c, XC_E_INVAL, "output is NULL");
+  Prepared p;
+  int rc = prepare(c, s, st, workspace, ws_bytes, stream, p);
   if (rc != XC_OK) return rc;
-  if (!out || !out->vis || !out->weight) return fail(c, XC_E_INVAL, "output is NULL");
-  unsigned char* ws = static_cast<unsigned char*>(workspace);
-  const DevJob* dj = reinterpret_cast<const DevJob*>(ws + L.desc);
-  DelayRec* drec = reinterpret_cast<DelayRec*>(ws + L.drec);
-  PhaseRec* prec = reinterpret_cast<PhaseRec*>(ws + L.prec);
-  float2* spec = reinterpret_cast<float2*>(ws + L.spec);
-  double2* vacc = reinterpret_cast<double2*>(ws + L.vacc);
-  double* wacc = reinterpret_cast<double*>(ws + L.wacc);
-  const int S = s->n_stations, nsb = s->n_subbands, M = S * s->n_pols;
-  const int N = 2 * s->n_chan;
-  hipError_t e = timed(c, XC_K_ZERO, stream, [&] {
-    return launch_zero(reinterpret_cast<double*>(vacc), (L.total - L.vacc) / sizeof(double),
-                       stream);
-  });
-  if (e != hipSuccess) return hip_fail(c, e, "zero");
-  int8_t* sexp = reinterpret_cast<int8_t*>(ws + L.sexp);
-  if (L.out != kOutF32) {
-    // channel scales from the first frames' FP32 spectra
-    e = launch_delays(dj, S, nsb, 0, L.n_scale, drec, prec, stream);
-    if (e == hipSuccess)
-      e = timed(c, XC_K_FSTAGE, stream, [&] {
-        return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nullptr, L.n_scale, 0, kOutF32,
-                             stream);
-      });
-    if (e == hipSuccess)
-      e = launch_scales(spec, nsb, L.n_scale, M, s->n_chan,
-                        L.out == kOutF16 ? kF16TargetLog2 : kF8TargetLog2, sexp, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "scales");
-  }
-  for (int64_t f0 = 0; f0 < s->n_frames; f0 += L.T) {
-    const int nf = (int)((s->n_frames - f0) < L.T ? (s->n_frames - f0) : L.T);
-    e = timed(c, XC_K_DELAYS, stream, [&] {
-      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec, prec, stream);
-      return r == hipSuccess ? launch_weights(drec, S, nf, wacc, stream) : r;
-    });
-    if (e != hipSuccess) return hip_fail(c, e, "delays");
-    e = timed(c, XC_K_FSTAGE, stream, [&] {
-      return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, sexp, nf,
-                           c->tune.fstage_waves_per_simd, L.out, stream);
-    });
-    if (e != hipSuccess) return hip_fail(c, e, "fstage");
-    if (L.out == kOutF32) {
-      e = timed(c, XC_K_XMAC, stream, [&] {
-        return launch_xmac(dj, M, s->n_chan, nsb, spec, vacc, L.slot_stride, nf,
-                           c->tune.xmac_frames_per_stage, c->tune.xmac_channels_per_wg,
-                           c->tune.xmac_tiles_per_wg, stream);
-      });
-    } else {
-      e = timed(c, XC_K_XMFMA, stream, [&] {
-        return launch_xmfma(dj, L.out, M, s->n_chan, nsb, spec, sexp, vacc, L.slot_stride, nf,
-                            stream);
-      });
-    }
-    if (e != hipSuccess) return hip_fail(c, e, "xmac");
-  }
-  e = timed(c, XC_K_FINALISE, stream, [&] {
-    return launch_finalise(vacc, L.n_slots, L.slot_stride, wacc, S, s->n_pols,
-                           static_cast<float2*>(out->vis), out->weight, nsb, M, s->n_chan,
-                           stream);
-  });
-  if (e != hipSuccess) return hip_fail(c, e, "finalise");
-  return XC_OK;
+  return enqueue_job(c, s, st, out, reinterpret_cast<const DevJob*>(p.desc), p.arena, p.L, p.tu,
+                     stream);
 }
 
 int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
@@ -507,13 +518,14 @@ int xc_debug_delays(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t*
                     double* d_frac, int32_t* valid, double* phi0, void* workspace,
                     size_t ws_bytes, void* stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  Layout L;
-  int rc = prepare(c, s, st, workspace, ws_bytes, stream, L);
+  Prepared p;
+  int rc = prepare(c, s, st, workspace, ws_bytes, stream, p);
+  if (rc == XC_OK) rc = ingest_missing(c, s, st, p, stream);
   if (rc != XC_OK) return rc;
-  unsigned char* ws = static_cast<unsigned char*>(workspace);
-  const DevJob* dj = reinterpret_cast<const DevJob*>(ws + L.desc);
-  DelayRec* drec = reinterpret_cast<DelayRec*>(ws + L.drec);
-  PhaseRec* prec = reinterpret_cast<PhaseRec*>(ws + L.prec);
+  const Layout& L = p.L;
+  const DevJob* dj = reinterpret_cast<const DevJob*>(p.desc);
+  DelayRec* drec = reinterpret_cast<DelayRec*>(p.arena + L.drec);
+  PhaseRec* prec = reinterpret_cast<PhaseRec*>(p.arena + L.prec);
   const int S = s->n_stations, nsb = s->n_subbands;
   const int64_t F = s->n_frames;
   std::vector<DelayRec> hd((size_t)S * L.T);
@@ -548,17 +560,17 @@ int xc_debug_unpack(xc_ctx* c, const xc_setup* s, const xc_station* st, int32_t 
                     int32_t input, int64_t frame, float* out, void* workspace, size_t ws_bytes,
                     void* stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  Layout L;
-  int rc = prepare(c, s, st, workspace, ws_bytes, stream, L);
+  Prepared p;
+  int rc = prepare(c, s, st, workspace, ws_bytes, stream, p);
+  if (rc == XC_OK) rc = ingest_missing(c, s, st, p, stream);
   if (rc != XC_OK) return rc;
   if (station < 0 || station >= s->n_stations || input < 0 ||
       input >= s->n_subbands * s->n_pols || frame < 0 || frame >= s->n_frames || !out)
     return fail(c, XC_E_INVAL, "debug_unpack: index out of range");
-  unsigned char* ws = static_cast<unsigned char*>(workspace);
-  const DevJob* dj = reinterpret_cast<const DevJob*>(ws + L.desc);
-  DelayRec* drec = reinterpret_cast<DelayRec*>(ws + L.drec);
-  PhaseRec* prec = reinterpret_cast<PhaseRec*>(ws + L.prec);
-  float* tmp = reinterpret_cast<float*>(ws + L.spec);
+  const DevJob* dj = reinterpret_cast<const DevJob*>(p.desc);
+  DelayRec* drec = reinterpret_cast<DelayRec*>(p.arena + p.L.drec);
+  PhaseRec* prec = reinterpret_cast<PhaseRec*>(p.arena + p.L.prec);
+  float* tmp = reinterpret_cast<float*>(p.arena + p.L.spec);
   const int N = 2 * s->n_chan;
   hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame, 1, drec, prec, stream);
   if (e == hipSuccess) e = launch_debug_unpack(dj, drec, 1, station, input, 0, tmp, N, stream);
@@ -571,19 +583,19 @@ int xc_debug_unpack(xc_ctx* c, const xc_setup* s, const xc_station* st, int32_t 
 int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t frame0,
                      int32_t n, void* spectra, void* workspace, size_t ws_bytes, void* stream_) {
   hipStream_t stream = (hipStream_t)stream_;
-  Layout L;
-  int rc = prepare(c, s, st, workspace, ws_bytes, stream, L);
+  Prepared p;
+  int rc = prepare(c, s, st, workspace, ws_bytes, stream, p);
+  if (rc == XC_OK) rc = ingest_missing(c, s, st, p, stream);
   if (rc != XC_OK) return rc;
-  if (n < 1 || n > L.T || frame0 < 0 || frame0 + n > s->n_frames || !spectra)
+  if (n < 1 || n > p.L.T || frame0 < 0 || frame0 + n > s->n_frames || !spectra)
     return fail(c, XC_E_INVAL, "debug_spectra: frame range");
-  unsigned char* ws = static_cast<unsigned char*>(workspace);
-  const DevJob* dj = reinterpret_cast<const DevJob*>(ws + L.desc);
-  DelayRec* drec = reinterpret_cast<DelayRec*>(ws + L.drec);
-  PhaseRec* prec = reinterpret_cast<PhaseRec*>(ws + L.prec);
+  const DevJob* dj = reinterpret_cast<const DevJob*>(p.desc);
+  DelayRec* drec = reinterpret_cast<DelayRec*>(p.arena + p.L.drec);
+  PhaseRec* prec = reinterpret_cast<PhaseRec*>(p.arena + p.L.prec);
   hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, stream);
   if (e == hipSuccess)
     e = launch_fstage(2 * s->n_chan, dj, s->n_stations, drec, prec, c->d_tw, spectra, nullptr, n,
-                      c->tune.fstage_waves_per_simd, kOutF32, stream);
+                      p.tu.fstage_waves_per_simd, kOutF32, stream);
   return e == hipSuccess ? XC_OK : hip_fail(c, e, "debug_spectra");
 }
 

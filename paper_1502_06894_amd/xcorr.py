@@ -43,6 +43,13 @@ class XcOutput(C.Structure):
     _fields_ = [("vis", C.c_void_p), ("weight", C.c_void_p)]
 
 
+class XcJob(C.Structure):
+    _fields_ = [("setup", XcSetup), ("st", C.POINTER(XcStation)), ("out", XcOutput)]
+
+
+XC_BATCH_GRAPH = 1
+
+
 class XcTuning(C.Structure):
     _fields_ = [("fstage_waves_per_simd", C.c_int32), ("xmac_frames_per_stage", C.c_int32),
                 ("xmac_channels_per_wg", C.c_int32), ("frames_per_block", C.c_int32),
@@ -82,6 +89,12 @@ def load_library() -> C.CDLL:
                                           C.c_int32, C.c_int64, P, P, C.c_size_t, P]),
             "xc_debug_spectra": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
                                            C.c_int64, C.c_int32, P, P, C.c_size_t, P]),
+            "xc_batch_workspace_bytes": (C.c_size_t, [P, C.POINTER(XcJob), C.c_int32, C.c_int32]),
+            "xc_correlate_batch": (C.c_int, [P, C.POINTER(XcJob), C.c_int32, C.c_int32, C.c_int32,
+                                             P, C.c_size_t, P]),
+            "xc_autotune": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
+                                      C.POINTER(XcOutput), P, C.c_size_t, P,
+                                      C.POINTER(XcTuning)]),
             "xc_set_tuning": (C.c_int, [P, C.POINTER(XcTuning)]),
             "xc_get_tuning": (C.c_int, [P, C.POINTER(XcTuning)]),
             "xc_profile_begin": (C.c_int, [P, C.c_int32]),
@@ -212,6 +225,76 @@ class Correlator:
                                                  workspace.numel(), _stream_ptr(stream)))
         return vis, w
 
+    # ------------------------------------------------------------------ batches
+    def _batch_structs(self, jobs, precision, outs):
+        ms = [_Marshal(j, precision) for j in jobs]
+        if outs is None:
+            outs = [self.alloc_output(j) for j in jobs]
+        arr = (XcJob * len(jobs))()
+        for i, (m, (vis, w)) in enumerate(zip(ms, outs)):
+            arr[i] = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)),
+                           XcOutput(vis.data_ptr(), w.data_ptr()))
+        return ms, outs, arr
+
+    def correlate_batch(self, jobs, *, n_lanes: int = 4, graph: bool = False,
+                        precision=XC_FP32, outs=None, workspace: Optional[torch.Tensor] = None,
+                        stream=None):
+        """Correlate a list of jobs as one batch; returns [(vis, weight), ...].
+
+        precision: one value for all jobs, or a list with one per job."""
+        if not isinstance(precision, (list, tuple)):
+            precision = [precision] * len(jobs)
+        ms = [_Marshal(j, p) for j, p in zip(jobs, precision)]
+        if outs is None:
+            outs = [self.alloc_output(j) for j in jobs]
+        arr = (XcJob * len(jobs))()
+        for i, (m, (vis, w)) in enumerate(zip(ms, outs)):
+            arr[i] = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)),
+                           XcOutput(vis.data_ptr(), w.data_ptr()))
+        if workspace is None:
+            n = int(self.lib.xc_batch_workspace_bytes(self.ctx, arr, len(jobs), n_lanes))
+            if n == 0:   # invalid job: the batch call itself reports which and why
+                self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, 0,
+                                                        None, 0, None))
+            workspace = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes,
+                                                XC_BATCH_GRAPH if graph else 0,
+                                                workspace.data_ptr(), workspace.numel(),
+                                                _stream_ptr(stream)))
+        return outs
+
+    def batch_workspace(self, jobs, n_lanes: int = 4, precision=XC_FP32) -> torch.Tensor:
+        if not isinstance(precision, (list, tuple)):
+            precision = [precision] * len(jobs)
+        ms = [_Marshal(j, p) for j, p in zip(jobs, precision)]
+        arr = (XcJob * len(jobs))()
+        for i, m in enumerate(ms):
+            arr[i] = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)), XcOutput(1, 1))
+        n = int(self.lib.xc_batch_workspace_bytes(self.ctx, arr, len(jobs), n_lanes))
+        if n == 0:
+            self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, 0, None,
+                                                    0, None))
+        return torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def autotune(self, job, *, precision=XC_FP32, workspace: Optional[torch.Tensor] = None,
+                 stream=None) -> dict:
+        """Time launch-shape candidates on `job` and cache the best for its shape."""
+        m = _Marshal(job, precision)
+        if workspace is None:
+            saved = self.get_tuning()
+            self.set_tuning(frames_per_block=2048)
+            try:
+                workspace = self.alloc_workspace(job, precision=precision)
+            finally:
+                self.set_tuning(**saved)
+        vis, w = self.alloc_output(job)
+        t = XcTuning()
+        self._check(self.lib.xc_autotune(self.ctx, C.byref(m.setup), m.stations,
+                                         C.byref(XcOutput(vis.data_ptr(), w.data_ptr())),
+                                         workspace.data_ptr(), workspace.numel(),
+                                         _stream_ptr(stream), C.byref(t)))
+        return {f: getattr(t, f) for f, _ in XcTuning._fields_}
+
     def set_tuning(self, **kw):
         """Set launch-shape parameters (fstage_waves_per_simd, xmac_frames_per_stage,
         xmac_channels_per_wg, frames_per_block); unspecified ones keep their value."""
@@ -284,3 +367,93 @@ def job_to_device(job, device="cuda:0"):
             st.frames = torch.from_numpy(np.ascontiguousarray(st.frames).view(np.int32))
         st.frames = st.frames.to(device).contiguous()
     return job
+
+
+class XcServerStats(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+                ("completed", C.c_int64), ("failed", C.c_int64), ("cancelled", C.c_int64),
+                ("queued", C.c_int64), ("running", C.c_int64),
+                ("station_samples_per_s", C.c_double)]
+
+
+def _server_sigs(lib):
+    P = C.c_void_p
+    sig = {
+        "xc_server_create": (C.c_int, [C.POINTER(P), C.c_int, C.c_size_t, C.c_int32]),
+        "xc_server_submit": (C.c_int, [P, C.POINTER(XcJob), C.POINTER(C.c_uint64)]),
+        "xc_server_poll": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_int32)]),
+        "xc_server_wait": (C.c_int, [P, C.c_uint64, C.c_int32]),
+        "xc_server_cancel": (C.c_int, [P, C.c_uint64]),
+        "xc_server_get_stats": (C.c_int, [P, C.POINTER(XcServerStats)]),
+        "xc_server_last_error": (C.c_char_p, [P]),
+        "xc_server_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+class Server:
+    """Continuous-batching server (xc_server_*): submit jobs, poll/wait, stats."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 16 << 30, max_slots: int = 4):
+        self.lib = load_library()
+        _server_sigs(self.lib)
+        self.device = device
+        self.srv = C.c_void_p()
+        rc = self.lib.xc_server_create(C.byref(self.srv), device, hbm_budget_bytes, max_slots)
+        if rc != XC_OK:
+            raise XcError(rc, strerror(rc))
+        self._keep = {}
+
+    def _check(self, rc):
+        if rc != XC_OK:
+            raise XcError(rc, f"{strerror(rc)}: {self.lib.xc_server_last_error(self.srv).decode()}")
+
+    def submit(self, job, *, precision: int = XC_FP32, out=None):
+        """Queue a job; returns (ticket, (vis, weight)).  Outputs fill when it is done."""
+        m = _Marshal(job, precision)
+        if out is None:
+            dev = f"cuda:{self.device}"
+            out = (torch.empty(job.n_subbands, job.n_baselines, job.n_chan, dtype=torch.complex64,
+                               device=dev),
+                   torch.empty(job.n_subbands, job.n_baselines, dtype=torch.float32, device=dev))
+        torch.cuda.synchronize(self.device)   # recordings and outputs are ready before the server reads them
+        arr = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)),
+                    XcOutput(out[0].data_ptr(), out[1].data_ptr()))
+        t = C.c_uint64()
+        self._check(self.lib.xc_server_submit(self.srv, C.byref(arr), C.byref(t)))
+        self._keep[t.value] = (job, out)
+        return t.value, out
+
+    def poll(self, ticket: int):
+        d = C.c_int32()
+        rc = self.lib.xc_server_poll(self.srv, ticket, C.byref(d))
+        return bool(d.value), rc
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> int:
+        rc = self.lib.xc_server_wait(self.srv, ticket, timeout_ms)
+        if rc != XC_E_TIMEOUT:
+            self._keep.pop(ticket, None)
+        return rc
+
+    def cancel(self, ticket: int) -> int:
+        return self.lib.xc_server_cancel(self.srv, ticket)
+
+    def stats(self) -> dict:
+        s = XcServerStats()
+        self._check(self.lib.xc_server_get_stats(self.srv, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in XcServerStats._fields_}
+
+    def close(self):
+        if self.srv:
+            self.lib.xc_server_destroy(self.srv)
+            self.srv = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
