@@ -8,6 +8,9 @@ finalise) on inputs already resident in HBM.  Default workload: 10 stations
 Prints one JSON line (stdout).  Progress goes to stderr.
 
   python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu-baseline]
+  python bench.py --workload c4 --precision fp16|fp8|fp32   # X stage on MFMA (FP16/FP8) or FP32
+  python bench.py --workload c3        # 64 uneven jobs: batch (lanes + hipGraph) vs per-job loop
+  python bench.py --workload c5        # Poisson request trace through the server
   python bench.py --calibrate-copy     # plain device copy of known size, for counter scaling
   python bench.py --rocpd-summary DB   # per-kernel table from a rocprofv3 database
 """
@@ -179,6 +182,163 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": n, "dispatches": 5}))
 
 
+def _per_job_fpb(job, elem_bytes=8, cap=1 << 30):
+    """Frames per block the batch executor picks (staged spectra capped at 1 GiB)."""
+    per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
+    T = min(2048, job.n_frames)
+    if T * per_frame > cap:
+        T = max(64, cap // per_frame)
+    return int(T)
+
+
+def run_c3(a):
+    """64 uneven sub-integrations over a device-resident pool: batch vs per-job loop."""
+    import torch
+    from paper_1502_06894_amd import xcorr
+    from synth import configs
+    log("generating the 20-station x 16-stream x 4.5 s pool on the GPU")
+    pool = configs.pool_recordings(device="cuda")
+    jobs = configs.batch_jobs(pool, a.jobs)
+    torch.cuda.synchronize()
+    ss = sum(j.station_samples for j in jobs)
+    log(f"{len(jobs)} jobs, {ss:.3e} station-samples")
+    corr = xcorr.Correlator(0)
+    # per-job loop, same block sizes as the batch
+    outs = [corr.alloc_output(j) for j in jobs]
+    fpbs = [_per_job_fpb(j) for j in jobs]
+    ws = torch.empty(max(corr.workspace_bytes(j, frames_per_block=f) for j, f in zip(jobs, fpbs)),
+                     dtype=torch.uint8, device="cuda")
+
+    def loop():
+        for j, f, o in zip(jobs, fpbs, outs):
+            corr.correlate(j, frames_per_block=f, out=o, workspace=ws)
+
+    loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        loop()
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / a.steps
+    log(f"per-job loop: {t_loop * 1e3:.1f} ms per batch, {ss / t_loop / 1e9:.1f} G ss/s")
+    refs = [(v.clone(), w.clone()) for v, w in outs]
+    bws = corr.batch_workspace(jobs, n_lanes=a.lanes)
+    bouts = [corr.alloc_output(j) for j in jobs]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        corr.correlate_batch(jobs, n_lanes=a.lanes, graph=True, outs=bouts, workspace=bws,
+                             stream=stream)     # capture
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            corr.correlate_batch(jobs, n_lanes=a.lanes, graph=True, outs=bouts, workspace=bws,
+                                 stream=stream)
+        stream.synchronize()
+    t_batch = (time.perf_counter() - t0) / a.steps
+    same = all(torch.equal(v, rv) and torch.equal(w, rw) for (v, w), (rv, rw) in zip(bouts, refs))
+    log(f"batch ({a.lanes} lanes, graph replay): {t_batch * 1e3:.1f} ms, "
+        f"{ss / t_batch / 1e9:.1f} G ss/s; identical to per-job results: {same}")
+    return {
+        "metric": "correlated station-samples/s", "value": round(ss / t_batch / 1e9, 2),
+        "unit": "G station-samples/s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
+        "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"C3: {len(jobs)} uneven sub-integration jobs (stations 2-20, "
+                               f"subbands 1-16, channels 128-8192, 0.1-4 s) over a 20-station "
+                               f"x 16-stream x 4.5 s device-resident pool",
+                   "lanes": a.lanes, "graph": True, "station_samples_per_step": ss},
+        "per_job_loop": {"value": round(ss / t_loop / 1e9, 2), "ms_per_step": round(t_loop * 1e3, 3)},
+        "batch_over_loop": round(t_loop / t_batch, 3),
+        "identical_to_per_job": bool(same),
+    }
+
+
+def run_c4(a):
+    """32 stations, 4 x 32 MHz, 4096 channels, 1 s, FP32 / FP16 / FP8 X stage."""
+    import torch
+    from paper_1502_06894_amd import xcorr
+    job, desc = make_job("c4")
+    xcorr.job_to_device(job, "cuda:0")
+    corr = xcorr.Correlator(0)
+    oks = [corr.ingest(st.frames) for st in job.stations]
+    res = {}
+    for prec in ("fp32", "fp16", "fp8"):
+        p = xcorr.PRECISIONS[prec]
+        ws = corr.alloc_workspace(job, precision=p, frame_ok=oks)
+        out = corr.alloc_output(job)
+        for _ in range(a.warmup):
+            corr.correlate(job, precision=p, out=out, workspace=ws, frame_ok=oks)
+        torch.cuda.synchronize()
+        corr.profile_begin(a.steps * 64 + 64)
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            corr.correlate(job, precision=p, out=out, workspace=ws, frame_ok=oks)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        prof = corr.profile_end()
+        res[prec] = {"value": round(job.station_samples / dt / 1e9, 2), "ms_per_step": round(dt * 1e3, 3),
+                     "kernels_ms_per_step": {k: round(ms / a.steps, 3) for k, (ms, n) in prof.items() if n}}
+        log(f"C4 {prec}: {dt * 1e3:.2f} ms/step, {job.station_samples / dt / 1e9:.1f} G ss/s "
+            f"{res[prec]['kernels_ms_per_step']}")
+        del ws
+    main_p = a.precision
+    return {
+        "metric": "correlated station-samples/s", "value": res[main_p]["value"],
+        "unit": "G station-samples/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": res[main_p]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "fp16": "f16 in, f32 accumulate",
+                                       "fp8": "e4m3 in, f32 accumulate"}[main_p],
+        "data": "synthetic",
+        "config": {"workload": desc, "stations": job.n_stations, "subbands": job.n_subbands,
+                   "channels": job.n_chan, "frames": job.n_frames, "precision": main_p,
+                   "station_samples_per_step": job.station_samples},
+        "precisions": res,
+    }
+
+
+def run_c5(a):
+    """Poisson request trace through the continuous-batching server."""
+    import torch
+    from paper_1502_06894_amd import xcorr
+    from synth import configs
+    log("generating the 20-station x 16-stream x 4.5 s pool on the GPU")
+    pool = configs.pool_recordings(device="cuda")
+    trace = configs.serve_trace(pool, a.requests, rate_hz=a.rate, max_log2_chan=a.max_log2_chan)
+    torch.cuda.synchronize()
+    ss = sum(j.station_samples for _, j in trace)
+    span = trace[-1][0]
+    log(f"{len(trace)} requests over {span:.2f} s, offered {ss / span / 1e9:.1f} G ss/s")
+    srv = xcorr.Server(0, hbm_budget_bytes=a.budget_gb << 30, max_slots=a.lanes)
+    tickets = []
+    t0 = time.perf_counter()
+    for arr, job in trace:
+        now = time.perf_counter() - t0
+        if arr > now:
+            time.sleep(arr - now)
+        tickets.append(srv.submit(job)[0])
+    rcs = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    log(f"served {st['completed']} requests in {wall:.2f} s: p50 {st['p50_ms']:.1f} ms, "
+        f"p99 {st['p99_ms']:.1f} ms, {st['station_samples_per_s'] / 1e9:.1f} G ss/s")
+    return {
+        "metric": "correlated station-samples/s", "value": round(st["station_samples_per_s"] / 1e9, 2),
+        "unit": "G station-samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(wall * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"C5: Poisson trace, {len(trace)} requests at {a.rate:g}/s "
+                               f"(stations 3-20, subbands 1-16, channels 256-{2 ** a.max_log2_chan}, "
+                               f"0.1-4 s) over the device-resident pool",
+                   "slots": a.lanes, "hbm_budget_gb": a.budget_gb},
+        "latency_ms": {"p50": round(st["p50_ms"], 2), "p99": round(st["p99_ms"], 2),
+                       "mean": round(st["mean_ms"], 2)},
+        "offered_g_per_s": round(ss / span / 1e9, 2),
+        "completed": st["completed"], "failed": st["failed"],
+        "all_ok": all(rc == 0 for rc in rcs),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +351,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--rocpd-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
+    ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
+                    help="c4: precision reported as the value")
+    ap.add_argument("--jobs", type=int, default=64, help="c3: number of jobs")
+    ap.add_argument("--lanes", type=int, default=8, help="c3/c5: concurrent lanes")
+    ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="c5: mean arrival rate (1/s)")
+    ap.add_argument("--max-log2-chan", type=int, default=13, help="c5: largest log2(channels)")
+    ap.add_argument("--budget-gb", type=int, default=96, help="c5: server HBM budget (GiB)")
     a = ap.parse_args()
     if a.rocpd_summary:
         print(rocpd_summary(a.rocpd_summary))
@@ -202,6 +370,11 @@ def main():
         sys.exit(2)
     if a.calibrate_copy:
         calibrate_copy()
+        return
+
+    if a.workload in ("c3", "c4", "c5"):
+        res = {"c3": run_c3, "c4": run_c4, "c5": run_c5}[a.workload](a)
+        print(json.dumps(res), flush=True)
         return
 
     import torch

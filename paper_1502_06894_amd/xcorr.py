@@ -419,7 +419,7 @@ class Server:
             out = (torch.empty(job.n_subbands, job.n_baselines, job.n_chan, dtype=torch.complex64,
                                device=dev),
                    torch.empty(job.n_subbands, job.n_baselines, dtype=torch.float32, device=dev))
-        torch.cuda.synchronize(self.device)   # recordings and outputs are ready before the server reads them
+        torch.cuda.current_stream(self.device).synchronize()   # recordings and outputs are ready
         arr = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)),
                     XcOutput(out[0].data_ptr(), out[1].data_ptr()))
         t = C.c_uint64()

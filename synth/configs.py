@@ -113,3 +113,90 @@ def small_job(device="cpu", *, n_stations=3, n_subbands=2, n_pols=2, n_chan=256,
                            sub_start=int(round(sub_start_s * fs)), n_frames=n_frames,
                            delay_polys=polys, shifts=shifts, phase_zero=pz, seed=seed,
                            device=device, margin=1024, stream_map=stream_map, name="small")
+
+
+# ---------------------------------------------------------------- C3 / C5: jobs over a pool
+
+POOL_STATIONS = 20
+POOL_STREAMS = 16
+POOL_SECONDS = 4.5
+POOL_T0_S = 37.0
+
+
+def pool_recordings(device="cpu", seed: int | None = None, seconds: float = POOL_SECONDS,
+                    n_stations: int = POOL_STATIONS):
+    """Device-resident recordings shared by batch and serving jobs: n_stations x 16
+    streams x `seconds` at 32 Msps (11.5 GB for the full pool), ground-station-like
+    delays; returns (stations' frames, first_sample, delay polynomials)."""
+    from . import format as fmt
+    from .shape import _Sky, make_station_frames
+    seed = cfg_seed(3) if seed is None else seed
+    rng = np.random.default_rng(seed)
+    fs, C = FS_16MHZ, POOL_STREAMS
+    polys = [[float(rng.uniform(-0.02, 0.02)), float(rng.uniform(-3e-6, 3e-6)), 0.0, 0.0, 0.0, 0.0]
+             for _ in range(n_stations)]
+    spf = fmt.samples_per_frame(C)
+    first = int(POOL_T0_S * fs)
+    n_m5b = -(-int(seconds * fs) // spf)
+    sky = _Sky(C, seed, device)
+    frames = [make_station_frames(C=C, fs=fs, first_sample=first, n_m5b=n_m5b,
+                                  shift=int(round(polys[s][0] * fs)), station_id=s, sky=sky,
+                                  seed=seed, rho=0.05, device=device) for s in range(n_stations)]
+    return frames, first, polys
+
+
+def pool_job(frames, first, polys, *, stations, n_subbands, n_chan, seconds, start_s, streams,
+             name="") -> Job:
+    """A single-pol job over pool stations `stations`, subbands on `streams`."""
+    from .job import Station
+    fs = FS_16MHZ
+    N = 2 * n_chan
+    n_frames = max(1, int(seconds * fs) // N)
+    sts = [Station(frames=frames[s], first_sample=first,
+                   delay_poly=np.asarray(polys[s], dtype=np.float64), station_id=s)
+           for s in stations]
+    return Job(n_stations=len(stations), n_subbands=n_subbands, n_pols=1, n_chan=n_chan,
+               n_streams=POOL_STREAMS, stream_map=list(streams), fs_hz=fs,
+               lo_hz=[LO0_HZ + s * 16e6 for s in streams],
+               sub_start=int(round((POOL_T0_S + start_s) * fs)), n_frames=n_frames,
+               stations=sts, name=name)
+
+
+def _random_pool_job(rng, pool, *, s_range, sb_range, log2_chan, len_range, pool_seconds):
+    frames, first, polys = pool
+    S = int(rng.integers(s_range[0], s_range[1] + 1))
+    nsb = int(rng.integers(sb_range[0], sb_range[1] + 1))
+    n_chan = int(2 ** rng.integers(log2_chan[0], log2_chan[1] + 1))
+    length = float(rng.uniform(*len_range))
+    length = min(length, pool_seconds - 0.1)
+    start = float(rng.uniform(0.05, pool_seconds - 0.05 - length))
+    stations = sorted(rng.choice(len(frames), size=min(S, len(frames)), replace=False).tolist())
+    streams = sorted(rng.choice(POOL_STREAMS, size=nsb, replace=False).tolist())
+    return pool_job(frames, first, polys, stations=stations, n_subbands=nsb, n_chan=n_chan,
+                    seconds=length, start_s=start, streams=streams)
+
+
+def batch_jobs(pool, n_jobs: int = 64, seed: int | None = None,
+               pool_seconds: float = POOL_SECONDS):
+    """C3: uneven sub-integrations: stations U{2..20}, subbands U{1..16},
+    channels 2^U{7..13}, lengths U[0.1, 4] s, single pol, 32 Msps."""
+    rng = np.random.default_rng(cfg_seed(3) + 1 if seed is None else seed)
+    return [_random_pool_job(rng, pool, s_range=(2, 20), sb_range=(1, 16), log2_chan=(7, 13),
+                             len_range=(0.1, 4.0), pool_seconds=pool_seconds)
+            for _ in range(n_jobs)]
+
+
+def serve_trace(pool, n_requests: int = 2000, rate_hz: float = 200.0, seed: int | None = None,
+                pool_seconds: float = POOL_SECONDS, max_log2_chan: int = 14):
+    """C5: Poisson arrivals (seeded exponential gaps) of requests with stations
+    U{3..20}, subbands U{1..16}, channels 2^U{8..14}, lengths U[0.1, 4] s.
+    Returns [(arrival_s, job)]."""
+    rng = np.random.default_rng(cfg_seed(5) if seed is None else seed)
+    t = 0.0
+    out = []
+    for _ in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_hz))
+        out.append((t, _random_pool_job(rng, pool, s_range=(3, 20), sb_range=(1, 16),
+                                        log2_chan=(8, max_log2_chan), len_range=(0.1, 4.0),
+                                        pool_seconds=pool_seconds)))
+    return out
