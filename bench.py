@@ -56,7 +56,7 @@ def make_job(name: str, frames: int = 0):
             "C2: 10 stations (1 space + 9 ground), 8 x 16 MHz subbands, dual pol, "
             "1024 channels, 4 s sub-int, 2-bit")
     if name == "c1":
-        return configs.c1_job(), ("C1: 2 stations (space + ground), 1 x 16 MHz, single pol, "
+        return configs.c1_job(device="cuda"), ("C1: 2 stations (space + ground), 1 x 16 MHz, single pol, "
                                   "256 channels, 0.5 s, 2-bit, exact-physics generator")
     if name == "c4":
         return configs.c4_job(device="cuda"), (

@@ -42,14 +42,15 @@ def ground_poly(rng: np.random.Generator) -> List[float]:
             float(rng.uniform(-1e-11, 1e-11)), 0.0, 0.0, 0.0]
 
 
-def c1_job(n_frames: int = 31250, seed: int | None = None) -> Job:
-    """C1: exact-physics two-station job (numpy/torch on the CPU)."""
+def c1_job(n_frames: int = 31250, seed: int | None = None, device="cpu") -> Job:
+    """C1: exact-physics two-station job (torch work on `device`)."""
     fs, N = FS_16MHZ, 512
     return physics.two_station_job(
         fs=fs, N=N, n_frames=n_frames, sub_start=int(SUB_START_S * fs),
         model_polys=[GROUND_C1, SPACE_C1],
         residual_delay_s=[0.0, C1_RESIDUAL_SAMPLES / fs],
-        lo_hz=LO0_HZ, rho=0.05, seed=cfg_seed(1) if seed is None else seed, name="C1")
+        lo_hz=LO0_HZ, rho=0.05, seed=cfg_seed(1) if seed is None else seed, name="C1",
+        device=device)
 
 
 def c2_job(device="cpu", n_frames: int = 62500, n_subbands: int = 8, n_stations: int = 10,

@@ -73,11 +73,11 @@ def buffer_extent(poly: Sequence[float], sub_start: int, n_frames: int, N: int,
 _TABLE_PHASES = 4096
 
 
-def _kernel_table() -> torch.Tensor:
+def _kernel_table(device="cpu") -> torch.Tensor:
     """Windowed-sinc taps for fractional offsets 0, 1/P, .., 1 (P = 4096), float64 [P+1, 64]."""
     half = TAPS // 2
-    fr = torch.arange(_TABLE_PHASES + 1, dtype=torch.float64) / _TABLE_PHASES
-    m = torch.arange(-half + 1, half + 1, dtype=torch.float64)          # -31 .. 32
+    fr = torch.arange(_TABLE_PHASES + 1, dtype=torch.float64, device=device) / _TABLE_PHASES
+    m = torch.arange(-half + 1, half + 1, dtype=torch.float64, device=device)   # -31 .. 32
     x = fr[:, None] - m[None, :]
     win = torch.special.i0(KAISER_BETA * torch.sqrt(torch.clamp(1.0 - (x / half) ** 2, min=0.0)))
     return torch.sinc(x) * win / float(np.i0(KAISER_BETA))
@@ -91,9 +91,9 @@ def _interp(sig: torch.Tensor, u: torch.Tensor, chunk: int = 1 << 18) -> torch.T
     (tap error below 1e-8 of the peak tap).
     """
     half = TAPS // 2
-    table = _kernel_table()
+    table = _kernel_table(sig.device)
     rows = sig.unfold(0, TAPS, 1)                                        # rows[i] = sig[i .. i+63]
-    out = torch.empty(u.shape[0], dtype=sig.dtype)
+    out = torch.empty(u.shape[0], dtype=sig.dtype, device=sig.device)
     for a in range(0, u.shape[0], chunk):
         uu = u[a:a + chunk]
         idx = torch.floor(uu)
@@ -110,10 +110,13 @@ def _interp(sig: torch.Tensor, u: torch.Tensor, chunk: int = 1 << 18) -> torch.T
 def two_station_job(*, fs: float, N: int, n_frames: int, sub_start: int,
                     model_polys: List[Sequence[float]], residual_delay_s: List[float],
                     lo_hz: float, rho: float, seed: int, C: int = 1,
-                    margin: int = 1024, poly_span=(0.0, 120.0), name: str = "") -> Job:
+                    margin: int = 1024, poly_span=(0.0, 120.0), name: str = "",
+                    device="cpu") -> Job:
     """Single-subband, single-pol job with a common sky signal (exact physics).
 
-    Works for any number of stations (the name reflects the usual use).
+    Works for any number of stations (the name reflects the usual use).  The
+    torch parts (sky FFT, interpolation, noise, packing) run on `device`; the
+    recordings are returned on that device.
     """
     n_st = len(model_polys)
     assert C == 1, "exact-physics generator records one stream"
@@ -135,9 +138,9 @@ def two_station_job(*, fs: float, N: int, n_frames: int, sub_start: int,
     k_hi = int(math.ceil(max(t.max() for t in t_ref) * fs)) + TAPS
     n_sky = k_hi - k_lo
     g = torch.Generator().manual_seed(seed_of(seed, 0x5C7))
-    s = torch.randn(n_sky, generator=g, dtype=torch.float64)
+    s = torch.randn(n_sky, generator=g, dtype=torch.float64).to(device)
     spec = torch.fft.fft(s)
-    h = torch.zeros(n_sky, dtype=torch.float64)
+    h = torch.zeros(n_sky, dtype=torch.float64, device=device)
     h[0] = 1.0
     if n_sky % 2 == 0:
         h[n_sky // 2] = 1.0
@@ -149,17 +152,17 @@ def two_station_job(*, fs: float, N: int, n_frames: int, sub_start: int,
     stations = []
     for si, ((first, n_m5b), poly, dlt, t) in enumerate(zip(extents, model_polys,
                                                              residual_delay_s, t_ref)):
-        u = torch.from_numpy(t * fs - k_lo)
+        u = torch.from_numpy(t * fs - k_lo).to(device)
         z = _interp(analytic, u)
         s_i, h_i = z.real, z.imag
         # theta = 2 pi frac(nu0 * tau_true(t)); long double keeps the fraction exact enough
         tau = _polyval(poly, t) + dlt
         ph = np.longdouble(lo_hz) * tau.astype(np.longdouble)
         ph = (ph - np.floor(ph)).astype(np.float64)
-        th = torch.from_numpy(2.0 * np.pi * ph)
+        th = torch.from_numpy(2.0 * np.pi * ph).to(device)
         x = s_i * torch.cos(th) + h_i * torch.sin(th)
         gn = torch.Generator().manual_seed(seed_of(seed, 0x401, si))
-        noise = torch.randn(x.shape[0], generator=gn, dtype=torch.float64)
+        noise = torch.randn(x.shape[0], generator=gn, dtype=torch.float64).to(device)
         v = math.sqrt(rho) * x + math.sqrt(1.0 - rho) * noise
         codes = fmt.quantise(v)[None, :]
         frames = fmt.frame_codes(codes, C, first, fs, si)
