@@ -169,8 +169,13 @@ int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
  * the FP32 path's tolerance). */
 typedef struct {
   int32_t fstage_waves_per_simd;   /* F-stage occupancy target: 0, 1, 2, 3 or 4 */
-  int32_t xmac_frames_per_stage;   /* X-stage frames per LDS stage: 0, 2 or 4; 1 = no LDS
-                                      staging (inputs read from memory, one frame ahead) */
+  int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
+                                      stages filled by direct memory-to-LDS loads (64-channel
+                                      tiles, at most 32 inputs per subband; the default where
+                                      it applies); 2 or 4 = double-buffered stages of that many
+                                      frames through registers (the default otherwise);
+                                      1 = no LDS staging (inputs read from memory, one frame
+                                      ahead); 0 = default */
   int32_t xmac_channels_per_wg;    /* X-stage channel tile: 0, 16, 32 or 64 */
   int32_t frames_per_block;        /* used when a setup says 0: 0 (= 2048) or 1..2048 */
   int32_t xmac_tiles_per_wg;       /* X-stage 4x4 input tiles per workgroup: 0 = all */

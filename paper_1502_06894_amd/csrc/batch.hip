@@ -247,8 +247,12 @@ int xc_autotune(xc_ctx* c, const xc_setup* setup, const xc_station* st, const xc
   for (int fpb : fpbs) {
     if (fpb > s.n_frames && fpb != 512) continue;
     if (s.precision == XC_FP32) {
-      const int xs[][2] = {{2, 0}, {4, 0}, {2, 32}, {1, 0}};
-      for (auto& x : xs) cands.push_back({0, x[0], x[1], fpb, 0});
+      const int M = s.n_stations * s.n_pols;
+      const int xs[][2] = {{8, 0}, {2, 0}, {4, 0}, {2, 32}, {1, 0}};
+      for (auto& x : xs) {
+        if (x[0] == 8 && M > 32) continue;   // the ring holds at most 32 inputs
+        cands.push_back({0, x[0], x[1], fpb, 0});
+      }
     } else {
       cands.push_back({0, 0, 0, fpb, 0});
     }

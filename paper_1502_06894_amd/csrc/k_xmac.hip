@@ -233,6 +233,191 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
+// Ring variant (channel tile 64, at most 32 padded inputs).  Spectra go from
+// memory straight into LDS (global_load_lds, no register staging) through a
+// ring of kRing one-frame stages that runs kRing - 1 frames ahead of the
+// multiply, so tens of KB per compute unit are in flight and memory latency
+// is hidden.  One wave per 4 x 4 tile, one lane per channel: a wave reads one
+// contiguous 512-byte LDS row per operand, free of bank conflicts.  A frame
+// stage is MP rows of 64 float2; wave w loads rows 2w and 2w + 1 (1 KB, one
+// instruction: LDS address = wave base + 16 * lane), so a wave issues exactly
+// one load per frame or none, and "frame j has landed" is a fixed
+// outstanding-load count.  The ring stages are separate LDS variables so the
+// compiler can tell the in-flight loads apart from the stage being read.
+constexpr int kRing = 8;
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// s_waitcnt immediates: at most n vector-memory operations of this wave
+// outstanding, and with _lds also no LDS operation outstanding.
+constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+constexpr int waitcnt_vm_lds(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
+
+// One ring step: wait for this wave's load of frame j (and its own LDS reads
+// of frame j - 1), barrier (stage CUR is complete everywhere and the stage of
+// frame j - 1 has been read by every wave), refill that stage NXT with frame
+// j + kRing - 1, multiply stage CUR.
+#define XC_RING_STEP(CUR, NXT)                                                       \
+  {                                                                                  \
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(kRing - 2));                           \
+    __asm__ volatile("" ::: "memory");                                               \
+    __builtin_amdgcn_s_barrier();                                                    \
+    __asm__ volatile("" ::: "memory");                                               \
+    ring_load(gsrc + (size_t)min(j + kRing - 1, fz - 1) * fstride4 + loff, NXT + lw * 64);\
+    ring_mac(reinterpret_cast<const float2*>(CUR), gi, gj, lane, acc);               \
+    ++j;                                                                             \
+  }
+
+__device__ __forceinline__ void ring_load(const float4* g, float4* l) {
+  __builtin_amdgcn_global_load_lds((glb_void_t*)g, (lds_void_t*)l, 16, 0, 0);
+}
+
+__device__ __forceinline__ void ring_mac(const float2* shb, int gi, int gj, int lane,
+                                         float2 (&acc)[kGroup][kGroup]) {
+  float2 a[kGroup], b[kGroup];
+#pragma unroll
+  for (int x = 0; x < kGroup; ++x) {
+    a[x] = shb[(gi * kGroup + x) * 64 + lane];
+    b[x] = shb[(gj * kGroup + x) * 64 + lane];
+  }
+#pragma unroll
+  for (int x = 0; x < kGroup; ++x)
+#pragma unroll
+    for (int y = 0; y < kGroup; ++y) {
+      acc[x][y].x = fmaf(a[x].x, b[y].x, fmaf(a[x].y, b[y].y, acc[x][y].x));
+      acc[x][y].y = fmaf(a[x].y, b[y].x, fmaf(-a[x].x, b[y].y, acc[x][y].y));
+    }
+}
+
+template <int MP>
+__global__ void __launch_bounds__(1024)
+    k_xmac_ring(const DevJob* __restrict__ job, const float2* __restrict__ spec,
+                double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
+                int frames_per_split, size_t slot_stride) {
+  static_assert(MP % kGroup == 0 && MP <= 32, "ring stages hold at most 32 inputs");
+  static_assert(kRing == 8, "one LDS variable per stage");
+  constexpr int KC = 64;
+  constexpr int F4 = MP * KC / 2;     // float4 per stage
+  __shared__ float4 r0[F4], r1[F4], r2[F4], r3[F4], r4[F4], r5[F4], r6[F4], r7[F4];
+  const DevJob& J = *job;
+  const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
+  constexpr int ng = MP / kGroup;
+  constexpr int ntiles = ng * (ng + 1) / 2;
+  const int sb = blockIdx.y;
+  const int k0 = blockIdx.x * KC;
+  const int zc = blockIdx.z % zchunks, split = blockIdx.z / zchunks;
+  const int fa = split * frames_per_split;
+  const int fz = min(nf, fa + frames_per_split);
+  if (fa >= fz) return;   // whole workgroup
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int tile = zc * tiles_per_wg + wave;
+  const bool active = wave < tiles_per_wg && tile < ntiles;
+  // The loop body has no branches (a branch would hide from the compiler which
+  // stage an in-flight load writes, and it would then wait for all of them):
+  // waves without a tile multiply tile 0 and store nothing, and waves beyond
+  // the MP / 2 loaders load rows 0 and 1 again, to the same LDS place as wave 0
+  // (identical bytes).
+  int gi = 0, gj = 0;
+  tile_of(active ? tile : 0, ng, gi, gj);
+  const int lw = wave < MP / 2 ? wave : 0;
+
+  // this lane's source: row 2 lw + lane / 32 (rows past M repeat row M - 1;
+  // their products are never stored), float4 column lane % 32
+  // (a wave-uniform frame base plus a loop-invariant 32-bit lane offset)
+  const int lrow = min(2 * lw + (lane >> 5), M - 1);
+  const float4* gsrc = reinterpret_cast<const float4*>(spec + (size_t)sb * nf * M * n_chan + k0);
+  const int loff = lrow * (n_chan / 2) + (lane & 31);
+  const size_t fstride4 = (size_t)M * n_chan / 2;
+
+  float2 acc[kGroup][kGroup];
+#pragma unroll
+  for (int a = 0; a < kGroup; ++a)
+#pragma unroll
+    for (int b = 0; b < kGroup; ++b) acc[a][b] = make_float2(0.f, 0.f);
+
+  // frames fa .. fa + kRing - 2 (past the slice: frame fz - 1 again)
+  ring_load(gsrc + (size_t)fa * fstride4 + loff, r0 + lw * 64);
+  ring_load(gsrc + (size_t)min(fa + 1, fz - 1) * fstride4 + loff, r1 + lw * 64);
+  ring_load(gsrc + (size_t)min(fa + 2, fz - 1) * fstride4 + loff, r2 + lw * 64);
+  ring_load(gsrc + (size_t)min(fa + 3, fz - 1) * fstride4 + loff, r3 + lw * 64);
+  ring_load(gsrc + (size_t)min(fa + 4, fz - 1) * fstride4 + loff, r4 + lw * 64);
+  ring_load(gsrc + (size_t)min(fa + 5, fz - 1) * fstride4 + loff, r5 + lw * 64);
+  ring_load(gsrc + (size_t)min(fa + 6, fz - 1) * fstride4 + loff, r6 + lw * 64);
+  // whole rounds of kRing frames, then the rest; no path leads back into the
+  // steps with a different set of loads in flight
+  int j = fa;
+  for (int round = (fz - fa) / kRing; round > 0; --round) {
+    XC_RING_STEP(r0, r7) XC_RING_STEP(r1, r0) XC_RING_STEP(r2, r1) XC_RING_STEP(r3, r2)
+    XC_RING_STEP(r4, r3) XC_RING_STEP(r5, r4) XC_RING_STEP(r6, r5) XC_RING_STEP(r7, r6)
+  }
+  do {
+    if (j >= fz) break;
+    XC_RING_STEP(r0, r7)
+    if (j >= fz) break;
+    XC_RING_STEP(r1, r0)
+    if (j >= fz) break;
+    XC_RING_STEP(r2, r1)
+    if (j >= fz) break;
+    XC_RING_STEP(r3, r2)
+    if (j >= fz) break;
+    XC_RING_STEP(r4, r3)
+    if (j >= fz) break;
+    XC_RING_STEP(r5, r4)
+    if (j >= fz) break;
+    XC_RING_STEP(r6, r5)
+  } while (false);
+  // no load may still be writing LDS when the workgroup ends
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+  if (!active) return;
+  double2* slot = vacc + (size_t)split * slot_stride;
+#pragma unroll
+  for (int x = 0; x < kGroup; ++x)
+#pragma unroll
+    for (int y = 0; y < kGroup; ++y) {
+      const int i = gi * kGroup + x, j = gj * kGroup + y;
+      if (i <= j && j < M) {
+        double2* o = slot + ((size_t)sb * nbl + bl_index(i, j, M)) * n_chan + k0 + lane;
+        double2 v = *o;
+        v.x += (double)acc[x][y].x;
+        v.y += (double)acc[x][y].y;
+        *o = v;
+      }
+    }
+}
+#undef XC_RING_STEP
+
+static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subbands,
+                              const float2* spec, double2* vacc, size_t slot_stride, int nf,
+                              int tpw_req, hipStream_t s) {
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  const int ng = Mp / kGroup;
+  const int ntiles = ng * (ng + 1) / 2;
+  if (Mp > 32 || n_chan % 64 != 0) return hipErrorInvalidValue;
+  const int n_splits = xmac_splits(nf);
+  const int fps = (nf + n_splits - 1) / n_splits;
+  int tiles_per_wg = tpw_req > 0 && tpw_req < 16 ? tpw_req : 16;
+  if (tiles_per_wg > ntiles) tiles_per_wg = ntiles;
+  const int zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
+  // every row pair of a stage needs a loading wave
+  const int waves = tiles_per_wg > Mp / 2 ? tiles_per_wg : Mp / 2;
+  dim3 grid(n_chan / 64, n_subbands, zchunks * n_splits);
+  dim3 block(64 * waves);
+#define XMAC_RING(MPV)                                                                    \
+  case MPV:                                                                               \
+    hipLaunchKernelGGL(k_xmac_ring<MPV>, grid, block, 0, s, job, spec, vacc, nf,          \
+                       tiles_per_wg, zchunks, fps, slot_stride);                          \
+    break;
+  switch (Mp) {
+    XMAC_RING(4) XMAC_RING(8) XMAC_RING(12) XMAC_RING(16) XMAC_RING(20) XMAC_RING(24)
+    XMAC_RING(28) XMAC_RING(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef XMAC_RING
+  return hipGetLastError();
+}
+
 static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subbands,
                                 const float2* spec, double2* vacc, size_t slot_stride, int nf,
                                 int kc_req, int tpw_req, hipStream_t s) {
@@ -331,6 +516,9 @@ static hipError_t launch_fb(const DevJob* job, int M, int n_chan, int n_subbands
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
                        const float2* spec, double2* vacc, size_t slot_stride, int nf, int fb,
                        int kc, int tpw, hipStream_t s) {
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  if ((fb == 0 || fb == kRing) && Mp <= 32 && (kc == 0 || kc == 64))
+    return launch_ring(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, tpw, s);
   if (fb == 1)
     return launch_direct(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
   if (fb == 4)

@@ -462,8 +462,9 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
 int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
   if (!c || !t) return XC_E_INVAL;
   const bool ok = t->fstage_waves_per_simd >= 0 && t->fstage_waves_per_simd <= 4 &&
-                  (t->xmac_frames_per_stage >= 0 && t->xmac_frames_per_stage <= 4 &&
-                   t->xmac_frames_per_stage != 3) &&
+                  (t->xmac_frames_per_stage == 0 || t->xmac_frames_per_stage == 1 ||
+                   t->xmac_frames_per_stage == 2 || t->xmac_frames_per_stage == 4 ||
+                   t->xmac_frames_per_stage == 8) &&
                   (t->xmac_channels_per_wg == 0 || t->xmac_channels_per_wg == 16 ||
                    t->xmac_channels_per_wg == 32 || t->xmac_channels_per_wg == 64) &&
                   t->frames_per_block >= 0 && t->frames_per_block <= kMaxBlockFrames &&

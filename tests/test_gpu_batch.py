@@ -114,6 +114,6 @@ def test_autotune_picks_a_candidate_and_stays_correct(xc, corr):
     xc.job_to_device(job)
     best = corr.autotune(job)
     assert best["frames_per_block"] in (512, 1024, 2048)
-    assert best["xmac_frames_per_stage"] in (1, 2, 4)
+    assert best["xmac_frames_per_stage"] in (1, 2, 4, 8)
     vis, w = corr.correlate(job)           # uses the tuned shape
     assert rel_l2(vis.cpu().numpy(), V) < 1e-5

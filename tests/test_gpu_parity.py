@@ -195,7 +195,8 @@ def test_tuning_variants_bit_identical(xc, corr):
     _on_gpu(xc, job)
     ref = None
     try:
-        for tune in [dict(), dict(xmac_frames_per_stage=1), dict(xmac_frames_per_stage=2),
+        for tune in [dict(), dict(xmac_frames_per_stage=8), dict(xmac_frames_per_stage=8, xmac_tiles_per_wg=2),
+                     dict(xmac_frames_per_stage=1), dict(xmac_frames_per_stage=2),
                      dict(xmac_frames_per_stage=4, xmac_channels_per_wg=16),
                      dict(xmac_frames_per_stage=1, xmac_channels_per_wg=32),
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=1),
