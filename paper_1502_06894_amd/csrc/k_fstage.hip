@@ -15,7 +15,14 @@ struct FGeom {
   static constexpr int E = FftPlan<N>::E;
   static constexpr int G = T >= 256 ? 1 : 256 / T;   // frames per workgroup
   static constexpr int WG = T * G;
-  static constexpr size_t lds_bytes = (size_t)G * lds_words<N>() * sizeof(float2);
+  // Up to N = 4096 the twiddles are staged in LDS (their tables then cost no
+  // registers); larger transforms read them from memory.
+  static constexpr bool tw_in_lds = N <= 4096;
+  // G FFT exchange buffers, the 8-entry level table, the twiddle tables
+  static constexpr size_t lut_off = (size_t)G * lds_words<N>() * sizeof(float2);
+  static constexpr size_t tw_off = lut_off + 8 * sizeof(float);
+  static constexpr size_t lds_bytes =
+      tw_off + (tw_in_lds ? (size_t)tw_lds_entries<N>() * sizeof(float2) : 0);
 };
 
 // Spectrum element written by the F stage: FP32 complex, or for the MFMA X
@@ -82,6 +89,18 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     for (int e = 0; e < E; ++e) wv[e] = 0u;
   }
   float2* lds = lds_all + g * lds_words<N>();
+  // 2-bit code -> level (offset binary: -3.3359, -1, +1, +3.3359), and four
+  // zeros that an invalid frame's lookups are pointed at
+  unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds_all);
+  float* lut = reinterpret_cast<float*>(lds_b + FGeom<N>::lut_off);
+  if (threadIdx.x < 8) {
+    const float lv[4] = {-3.3359f, -1.0f, 1.0f, 3.3359f};
+    lut[threadIdx.x] = threadIdx.x < 4 ? lv[threadIdx.x] : 0.0f;
+  }
+  float2* tw_tab = reinterpret_cast<float2*>(lds_b + FGeom<N>::tw_off);
+  if constexpr (FGeom<N>::tw_in_lds) tw_lds_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
+  const float* lut_t = lut + (valid ? 0 : 4);
+  __syncthreads();
   const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
 
   // fractional-delay phasors of this thread's output bins k = t + r N/16:
@@ -96,12 +115,17 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   }
   const double nc0 = (double)(t - N / 2);     // centred index of the thread's first sample
   constexpr double TD = (double)T;
+  // With whole waves per frame (T >= 64) the frame index is wave-uniform: the
+  // phase records then come in through scalar loads, which a wave does not
+  // have to order behind its own outstanding spectrum stores.
+  const int flu = T >= 64 ? __builtin_amdgcn_readfirstlane(fl) : fl;
+  const bool in_blk_u = flu < nf;
 
   for (int in = 0; in < J.n_inputs; ++in) {
     const int sb = in / P, p = in - sb * P;
     const int sh = sh0 + 2 * J.stream_map[in];
     PhaseRec ph;
-    if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
+    if (in_blk_u) ph = prec[((size_t)s * n_sb + sb) * nf + flu];
     else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
     // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
     // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
@@ -119,10 +143,11 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
         z = cmul(z, w);
         w = cmul(w, rho);
       }
-      const float q = valid ? level_of((wv[e] >> sh) & 3u) : 0.0f;
+      const float q = lut_t[(wv[e] >> sh) & 3u];
       v[e] = make_float2(q * z.x, q * z.y);
     }
-    fft_forward<N>(v, lds, tw, t);
+    if constexpr (FGeom<N>::tw_in_lds) fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
+    else fft_forward<N>(v, lds, TwGlobal{tw}, t);
     if (in_blk) {
       const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
       const int8_t* ex = OUT == kOutF32 ? nullptr

@@ -290,8 +290,11 @@ __device__ __forceinline__ void ring_mac(const float2* shb, int gi, int gj, int 
     }
 }
 
+// Up to 20 inputs a stage is at most 80 KB, so two workgroups fit the 160 KB of
+// LDS of a compute unit; they also need 64 VGPRs or fewer (8 waves per SIMD).
 template <int MP>
-__global__ void __launch_bounds__(1024)
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, 1024),
+                               amdgpu_waves_per_eu(MP <= 20 ? 8 : 1)))
     k_xmac_ring(const DevJob* __restrict__ job, const float2* __restrict__ spec,
                 double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
                 int frames_per_split, size_t slot_stride) {

@@ -100,12 +100,60 @@ constexpr int lds_words() {
   return N + N / 32;
 }
 
+// Radix of the first pass for N = 2^L2: 16 when L2 is a multiple of 4, else 2^(L2 mod 4).
+template <int N>
+constexpr int first_radix() {
+  return (__builtin_ctz(N) % 4) == 0 ? 16 : (1 << (__builtin_ctz(N) % 4));
+}
+
+// Twiddle sources for the Stockham passes.  Only radix-16 passes with
+// sub-transform length Ns > 1 take twiddles: input r of butterfly j is
+// multiplied by exp(-2 pi i k r / (16 Ns)), k = j mod Ns.
+// TwGlobal reads them from the kTwiddleN-entry table in memory.
+struct TwGlobal {
+  const float2* __restrict__ tw;
+  template <int R, int Ns>
+  __device__ float2 get(int k, int r) const {
+    return tw[k * r * (kTwiddleN / (Ns * R))];
+  }
+};
+
+// TwLds reads them from per-pass tables staged in LDS: the pass with
+// sub-transform length Ns (= R0, 16 R0, 256 R0, ...) owns 15 Ns entries from
+// offset Ns - R0, entry (r - 1) Ns + k; a thread's 15 twiddles are one address
+// plus compile-time offsets.  All passes together take N - R0 entries.
+template <int N>
+struct TwLds {
+  const float2* tab;
+  template <int R, int Ns>
+  __device__ float2 get(int k, int r) const {
+    return tab[(Ns - first_radix<N>()) + (r - 1) * Ns + k];
+  }
+};
+
+template <int N>
+constexpr int tw_lds_entries() {
+  return N - first_radix<N>();
+}
+
+// Fill the TwLds tables of an N-point transform (threads tid, tid + nthr, ...).
+template <int N>
+__device__ inline void tw_lds_fill(float2* tab, const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int R0 = first_radix<N>();
+  for (int e = tid; e < tw_lds_entries<N>(); e += nthr) {
+    int Ns = R0;
+    while (e >= 16 * Ns - R0) Ns *= 16;
+    const int e2 = e - (Ns - R0);
+    const int r = e2 / Ns + 1, k = e2 - (r - 1) * Ns;
+    tab[e] = tw[k * r * (kTwiddleN / (Ns * 16))];
+  }
+}
+
 // One Stockham pass of radix R with sub-transform length Ns over a frame of N
 // points.  On entry v[b + r B] (B = E/R) is input r of butterfly j = t + b T;
 // the outputs are written to lds; the caller synchronises.
-template <int N, int T, int E, int R, int Ns>
-__device__ inline void stockham_pass(float2 (&v)[E], float2* lds, const float2* __restrict__ tw,
-                                     int t) {
+template <int N, int T, int E, int R, int Ns, class TW>
+__device__ inline void stockham_pass(float2 (&v)[E], float2* lds, const TW& tw, int t) {
   constexpr int B = E / R;
   static_assert(B * R == E, "radix must divide the per-thread count");
 #pragma unroll
@@ -114,11 +162,10 @@ __device__ inline void stockham_pass(float2 (&v)[E], float2* lds, const float2* 
     float2 u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * B];
-    if (Ns > 1) {
+    if constexpr (Ns > 1) {
       const int k = j % Ns;
-      constexpr int step = kTwiddleN / (Ns * R);
 #pragma unroll
-      for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw[k * r * step]);
+      for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw.template get<R, Ns>(k, r));
     }
     Dft<R>::run(u);
     const int idx = (j / Ns) * Ns * R + (j % Ns);
@@ -141,8 +188,8 @@ __device__ inline void stockham_gather(float2 (&v)[E], const float2* lds, int t)
 
 // Last pass: radix R with Ns = N / R; the butterfly outputs are final bins
 // k = j + r N / R and stay in registers (v[b + r B]).
-template <int N, int T, int E, int R>
-__device__ inline void stockham_last(float2 (&v)[E], const float2* __restrict__ tw, int t) {
+template <int N, int T, int E, int R, class TW>
+__device__ inline void stockham_last(float2 (&v)[E], const TW& tw, int t) {
   constexpr int B = E / R;
   constexpr int Ns = N / R;
 #pragma unroll
@@ -152,9 +199,8 @@ __device__ inline void stockham_last(float2 (&v)[E], const float2* __restrict__ 
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = v[b + r * B];
     const int k = j % Ns;
-    constexpr int step = kTwiddleN / (Ns * R);
 #pragma unroll
-    for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw[k * r * step]);
+    for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw.template get<R, Ns>(k, r));
     Dft<R>::run(u);
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b + r * B] = u[r];
@@ -179,14 +225,13 @@ template <> struct FftPlan<16384> { static constexpr int T = 1024, E = 16; };
 // On entry v[e] = x[t + e T]; on exit v[b + r B_last] = X[t + b T + r N / 16].
 // `lds` holds lds_words<N>() float2; the group's threads synchronise with
 // __syncthreads (the whole workgroup runs the same pass sequence).
-template <int N>
-__device__ inline void fft_forward(float2 (&v)[FftPlan<N>::E], float2* lds,
-                                   const float2* __restrict__ tw, int t) {
+template <int N, class TW>
+__device__ inline void fft_forward(float2 (&v)[FftPlan<N>::E], float2* lds, const TW& tw, int t) {
   constexpr int T = FftPlan<N>::T, E = FftPlan<N>::E;
   constexpr int L2 = __builtin_ctz(N);
   // number of radix-16 passes after the first (mixed) pass
   constexpr int n16 = (L2 / 4) - ((L2 % 4) == 0 ? 1 : 0);
-  constexpr int R0 = (L2 % 4) == 0 ? 16 : (1 << (L2 % 4));
+  constexpr int R0 = first_radix<N>();
   stockham_pass<N, T, E, R0, 1>(v, lds, tw, t);
   __syncthreads();
   stockham_gather<N, T, E, 16>(v, lds, t);
