@@ -179,6 +179,12 @@ typedef struct {
   int32_t xmac_channels_per_wg;    /* X-stage channel tile: 0, 16, 32 or 64 */
   int32_t frames_per_block;        /* used when a setup says 0: 0 (= 2048) or 1..2048 */
   int32_t xmac_tiles_per_wg;       /* X-stage 4x4 input tiles per workgroup: 0 = all */
+  int32_t block_overlap;           /* single-job calls over two or more blocks: 0 = default
+                                      (off), 1 = off, 2 = on.  On: the F stage of block b + 1
+                                      runs beside the X stage of block b on a second,
+                                      library-owned stream (two block buffers in the
+                                      workspace; identical results); the call stays
+                                      asynchronous on the caller's stream */
 } xc_tuning;
 
 int xc_set_tuning(xc_ctx* ctx, const xc_tuning* t);

@@ -251,10 +251,10 @@ int xc_autotune(xc_ctx* c, const xc_setup* setup, const xc_station* st, const xc
       const int xs[][2] = {{8, 0}, {2, 0}, {4, 0}, {2, 32}, {1, 0}};
       for (auto& x : xs) {
         if (x[0] == 8 && M > 32) continue;   // the ring holds at most 32 inputs
-        cands.push_back({0, x[0], x[1], fpb, 0});
+        cands.push_back({0, x[0], x[1], fpb, 0, 1});
       }
     } else {
-      cands.push_back({0, 0, 0, fpb, 0});
+      cands.push_back({0, 0, 0, fpb, 0, 1});
     }
   }
   hipEvent_t a = nullptr, b = nullptr;
@@ -264,7 +264,7 @@ int xc_autotune(xc_ctx* c, const xc_setup* setup, const xc_station* st, const xc
   const bool prof = c->profiling;
   c->profiling = false;
   float best_ms = 1e30f;
-  xc_tuning best = {0, 0, 0, 0, 0};
+  xc_tuning best = {0, 0, 0, 0, 0, 0};
   for (const xc_tuning& tu : cands) {
     const Layout L = layout_of(&s, st, tu);
     if (align_up(L.desc_bytes) + L.total > ws_bytes) continue;

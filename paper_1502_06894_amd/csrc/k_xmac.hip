@@ -290,11 +290,8 @@ __device__ __forceinline__ void ring_mac(const float2* shb, int gi, int gj, int 
     }
 }
 
-// Up to 20 inputs a stage is at most 80 KB, so two workgroups fit the 160 KB of
-// LDS of a compute unit; they also need 64 VGPRs or fewer (8 waves per SIMD).
 template <int MP>
-__global__ void __attribute__((amdgpu_flat_work_group_size(1, 1024),
-                               amdgpu_waves_per_eu(MP <= 20 ? 8 : 1)))
+__global__ void __launch_bounds__(1024)
     k_xmac_ring(const DevJob* __restrict__ job, const float2* __restrict__ spec,
                 double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
                 int frames_per_split, size_t slot_stride) {
@@ -340,6 +337,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, 1024),
 #pragma unroll
     for (int b = 0; b < kGroup; ++b) acc[a][b] = make_float2(0.f, 0.f);
 
+  int j = fa;
   // frames fa .. fa + kRing - 2 (past the slice: frame fz - 1 again)
   ring_load(gsrc + (size_t)fa * fstride4 + loff, r0 + lw * 64);
   ring_load(gsrc + (size_t)min(fa + 1, fz - 1) * fstride4 + loff, r1 + lw * 64);
@@ -350,7 +348,6 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, 1024),
   ring_load(gsrc + (size_t)min(fa + 6, fz - 1) * fstride4 + loff, r6 + lw * 64);
   // whole rounds of kRing frames, then the rest; no path leads back into the
   // steps with a different set of loads in flight
-  int j = fa;
   for (int round = (fz - fa) / kRing; round > 0; --round) {
     XC_RING_STEP(r0, r7) XC_RING_STEP(r1, r0) XC_RING_STEP(r2, r1) XC_RING_STEP(r3, r2)
     XC_RING_STEP(r4, r3) XC_RING_STEP(r5, r4) XC_RING_STEP(r6, r5) XC_RING_STEP(r7, r6)
@@ -409,7 +406,7 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
   dim3 block(64 * waves);
 #define XMAC_RING(MPV)                                                                    \
   case MPV:                                                                               \
-    hipLaunchKernelGGL(k_xmac_ring<MPV>, grid, block, 0, s, job, spec, vacc, nf,          \
+    hipLaunchKernelGGL((k_xmac_ring<MPV>), grid, block, 0, s, job, spec, vacc, nf,     \
                        tiles_per_wg, zchunks, fps, slot_stride);                          \
     break;
   switch (Mp) {

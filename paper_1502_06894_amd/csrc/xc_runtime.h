@@ -42,7 +42,7 @@ using ShapeKey = std::tuple<int, int, int, int, int>;
 
 struct xc_ctx {
   int device = 0;
-  xc_tuning tune = {0, 0, 0, 0, 0};          // explicit overrides (0 = auto)
+  xc_tuning tune = {0, 0, 0, 0, 0, 0};       // explicit overrides (0 = auto)
   std::map<xc::ShapeKey, xc_tuning> tuned;   // autotuned shapes
   bool profiling = false;
   bool capturing = false;                    // inside a graph capture: no profiling events
@@ -63,6 +63,8 @@ struct xc_ctx {
   unsigned char* h_batch = nullptr;          // pinned descriptor blob of the last batch
   size_t h_batch_bytes = 0;
   hipEvent_t batch_ev = nullptr;             // the blob's upload has completed
+  hipStream_t xstream = nullptr;             // X stage of overlapped single jobs
+  hipEvent_t blk_f[2] = {}, blk_x[2] = {};   // block buffer p: F done / X done
   std::string last_error;
 };
 
@@ -94,6 +96,8 @@ struct Layout {
   int n_scale = 0;                // frames of the scale pre-pass (MFMA path)
   int n_slots = 1;                // FP64 accumulator slots of the X stage
   size_t slot_stride = 0;         // double2 elements per slot
+  int nbuf = 1;                   // block buffers (2: F of block b+1 beside X of block b)
+  size_t drec_bytes = 0, prec_bytes = 0, spec_bytes = 0;   // per block buffer
 };
 
 ShapeKey shape_key(const xc_setup* s);
@@ -101,17 +105,24 @@ ShapeKey shape_key(const xc_setup* s);
 // entry for the job's shape, else built-in defaults (zeros).
 xc_tuning effective_tuning(const xc_ctx* c, const xc_setup* s);
 int validate(xc_ctx* c, const xc_setup* s, const xc_station* st);
-Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu);
+// overlap: the caller can run blocks overlapped (single jobs); the layout then
+// holds two block buffers when the tuning allows it and there are two blocks.
+Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu,
+                 bool overlap = false);
 // Descriptor for device address `dev_desc`; stations' frame_ok default to the arena masks.
 void build_desc(const xc_setup* s, const xc_station* st, const Layout& L,
                 const unsigned char* dev_desc, const unsigned char* arena, unsigned char* h);
 // Stage one descriptor through a pinned ring slot and copy it to dev_desc.
 int upload_desc(xc_ctx* c, const xc_setup* s, const xc_station* st, const Layout& L,
                 unsigned char* dev_desc, const unsigned char* arena, hipStream_t stream);
-// Enqueue every kernel of one job (ingest .. finalise) on `stream`.
+// Enqueue every kernel of one job (ingest .. finalise) on `stream`; with two
+// block buffers and `xs` given, the X stages run on `xs` (joined back to
+// `stream` before the finalise).
 int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
                 const DevJob* dj, unsigned char* arena, const Layout& L, const xc_tuning& tu,
-                hipStream_t stream);
+                hipStream_t stream, hipStream_t xs = nullptr);
 int ensure_lanes(xc_ctx* c, int n);
+// The context's X-stage stream and block events (created on first use).
+int ensure_xstream(xc_ctx* c);
 
 }  // namespace xc

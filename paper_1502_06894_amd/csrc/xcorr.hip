@@ -40,7 +40,7 @@ ShapeKey shape_key(const xc_setup* s) {
 }
 
 xc_tuning effective_tuning(const xc_ctx* c, const xc_setup* s) {
-  xc_tuning t = {0, 0, 0, 0, 0};
+  xc_tuning t = {0, 0, 0, 0, 0, 0};
   if (!c) return t;
   auto it = c->tuned.find(shape_key(s));
   if (it != c->tuned.end()) t = it->second;
@@ -50,6 +50,7 @@ xc_tuning effective_tuning(const xc_ctx* c, const xc_setup* s) {
   if (o.xmac_channels_per_wg) t.xmac_channels_per_wg = o.xmac_channels_per_wg;
   if (o.frames_per_block) t.frames_per_block = o.frames_per_block;
   if (o.xmac_tiles_per_wg) t.xmac_tiles_per_wg = o.xmac_tiles_per_wg;
+  if (o.block_overlap) t.block_overlap = o.block_overlap;
   return t;
 }
 
@@ -113,7 +114,7 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
   return XC_OK;
 }
 
-Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu) {
+Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, bool overlap) {
   Layout L;
   const int S = s->n_stations, nsb = s->n_subbands, M = S * s->n_pols;
   const size_t nbl = (size_t)M * (M + 1) / 2;
@@ -128,10 +129,13 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu) {
       L.mask_off[i] = off - L.mask;
       off += align_up((size_t)st[i].n_frames_m5b);
     }
+  L.nbuf = overlap && tu.block_overlap == 2 && s->n_frames > L.T ? 2 : 1;
+  L.drec_bytes = align_up((size_t)S * L.T * sizeof(DelayRec));
   L.drec = off;
-  off += align_up((size_t)S * L.T * sizeof(DelayRec));
+  off += L.nbuf * L.drec_bytes;
+  L.prec_bytes = align_up((size_t)S * nsb * L.T * sizeof(PhaseRec));
   L.prec = off;
-  off += align_up((size_t)S * nsb * L.T * sizeof(PhaseRec));
+  off += L.nbuf * L.prec_bytes;
   L.out = s->precision == XC_FP16_MFMA ? kOutF16 : s->precision == XC_FP8_MFMA ? kOutF8 : kOutF32;
   L.spec = off;
   size_t spec_bytes = (size_t)nsb * L.T * M * s->n_chan * out_elem_bytes(L.out);
@@ -140,7 +144,8 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu) {
     const size_t pre = (size_t)nsb * L.n_scale * M * s->n_chan * sizeof(float2);
     if (pre > spec_bytes) spec_bytes = pre;
   }
-  off += align_up(spec_bytes);
+  L.spec_bytes = align_up(spec_bytes);
+  off += L.nbuf * L.spec_bytes;
   L.sexp = off;
   if (L.out != kOutF32) off += align_up((size_t)nsb * M * s->n_chan);
   L.n_slots = L.out == kOutF32 ? xmac_splits(L.T) : 1;
@@ -219,10 +224,11 @@ int upload_desc(xc_ctx* c, const xc_setup* s, const xc_station* st, const Layout
 
 int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
                 const DevJob* dj, unsigned char* arena, const Layout& L, const xc_tuning& tu,
-                hipStream_t stream) {
+                hipStream_t stream, hipStream_t xs) {
   DelayRec* drec = reinterpret_cast<DelayRec*>(arena + L.drec);
   PhaseRec* prec = reinterpret_cast<PhaseRec*>(arena + L.prec);
   void* spec = arena + L.spec;
+  const bool overlap = L.nbuf == 2 && xs != nullptr;
   double2* vacc = reinterpret_cast<double2*>(arena + L.vacc);
   double* wacc = reinterpret_cast<double*>(arena + L.wacc);
   int8_t* sexp = reinterpret_cast<int8_t*>(arena + L.sexp);
@@ -254,31 +260,58 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
                         L.out == kOutF16 ? kF16TargetLog2 : kF8TargetLog2, sexp, stream);
     if (e != hipSuccess) return hip_fail(c, e, "scales");
   }
-  for (int64_t f0 = 0; f0 < s->n_frames; f0 += L.T) {
+  // Blocks of L.T frames.  Overlapped: block b uses buffer p = b mod 2; its F
+  // stage (on `stream`) waits until the X stage of block b - 2 (on `xs`) has
+  // read that buffer, and its X stage waits for its F stage.
+  int64_t blk = 0;
+  for (int64_t f0 = 0; f0 < s->n_frames; f0 += L.T, ++blk) {
     const int nf = (int)((s->n_frames - f0) < L.T ? (s->n_frames - f0) : L.T);
+    const int p = overlap ? (int)(blk & 1) : 0;
+    DelayRec* drec_p = reinterpret_cast<DelayRec*>(arena + L.drec + p * L.drec_bytes);
+    PhaseRec* prec_p = reinterpret_cast<PhaseRec*>(arena + L.prec + p * L.prec_bytes);
+    void* spec_p = arena + L.spec + p * L.spec_bytes;
+    hipStream_t xstr = overlap ? xs : stream;
+    if (overlap && blk >= 2) {
+      e = hipStreamWaitEvent(stream, c->blk_x[p], 0);
+      if (e != hipSuccess) return hip_fail(c, e, "block wait");
+    }
     e = timed(c, XC_K_DELAYS, stream, [&] {
-      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec, prec, stream);
-      return r == hipSuccess ? launch_weights(drec, S, nf, wacc, stream) : r;
+      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec_p, prec_p, stream);
+      return r == hipSuccess ? launch_weights(drec_p, S, nf, wacc, stream) : r;
     });
     if (e != hipSuccess) return hip_fail(c, e, "delays");
     e = timed(c, XC_K_FSTAGE, stream, [&] {
-      return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, sexp, nf,
+      return launch_fstage(N, dj, S, drec_p, prec_p, c->d_tw, spec_p, sexp, nf,
                            tu.fstage_waves_per_simd, L.out, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
+    if (overlap) {
+      e = hipEventRecord(c->blk_f[p], stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(xs, c->blk_f[p], 0);
+      if (e != hipSuccess) return hip_fail(c, e, "block handoff");
+    }
     if (L.out == kOutF32) {
-      e = timed(c, XC_K_XMAC, stream, [&] {
-        return launch_xmac(dj, M, s->n_chan, nsb, static_cast<const float2*>(spec), vacc,
+      e = timed(c, XC_K_XMAC, xstr, [&] {
+        return launch_xmac(dj, M, s->n_chan, nsb, static_cast<const float2*>(spec_p), vacc,
                            L.slot_stride, nf, tu.xmac_frames_per_stage, tu.xmac_channels_per_wg,
-                           tu.xmac_tiles_per_wg, stream);
+                           tu.xmac_tiles_per_wg, xstr);
       });
     } else {
-      e = timed(c, XC_K_XMFMA, stream, [&] {
-        return launch_xmfma(dj, L.out, M, s->n_chan, nsb, spec, sexp, vacc, L.slot_stride, nf,
-                            stream);
+      e = timed(c, XC_K_XMFMA, xstr, [&] {
+        return launch_xmfma(dj, L.out, M, s->n_chan, nsb, spec_p, sexp, vacc, L.slot_stride, nf,
+                            xstr);
       });
     }
     if (e != hipSuccess) return hip_fail(c, e, "xmac");
+    if (overlap) {
+      e = hipEventRecord(c->blk_x[p], xs);
+      if (e != hipSuccess) return hip_fail(c, e, "block record");
+    }
+  }
+  if (overlap) {
+    // X stages run in order on xs: the last one done means all are
+    e = hipStreamWaitEvent(stream, c->blk_x[(blk - 1) & 1], 0);
+    if (e != hipSuccess) return hip_fail(c, e, "block join");
   }
   e = timed(c, XC_K_FINALISE, stream, [&] {
     return launch_finalise(vacc, L.n_slots, L.slot_stride, wacc, S, s->n_pols,
@@ -287,6 +320,16 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
   });
   if (e != hipSuccess) return hip_fail(c, e, "finalise");
   return XC_OK;
+}
+
+int ensure_xstream(xc_ctx* c) {
+  if (c->xstream) return XC_OK;
+  hipError_t e = hipStreamCreateWithFlags(&c->xstream, hipStreamNonBlocking);   // default priority
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&c->blk_f[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->blk_x[k], hipEventDisableTiming);
+  }
+  return e == hipSuccess ? XC_OK : hip_fail(c, e, "X-stage stream");
 }
 
 int ensure_lanes(xc_ctx* c, int n) {
@@ -321,7 +364,7 @@ int prepare(xc_ctx* c, const xc_setup* s, const xc_station* st, void* workspace,
   int rc = validate(c, s, st);
   if (rc != XC_OK) return rc;
   p.tu = effective_tuning(c, s);
-  p.L = layout_of(s, st, p.tu);
+  p.L = layout_of(s, st, p.tu, true);
   const size_t need = align_up(p.L.desc_bytes) + p.L.total;
   if (!workspace || ws_bytes < need)
     return fail(c, XC_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
@@ -416,6 +459,14 @@ void xc_destroy(xc_ctx* c) {
     (void)hipEventDestroy(c->lane_ev[i]);
   }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->xstream) {
+    (void)hipStreamSynchronize(c->xstream);
+    (void)hipStreamDestroy(c->xstream);
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (c->blk_f[k]) (void)hipEventDestroy(c->blk_f[k]);
+    if (c->blk_x[k]) (void)hipEventDestroy(c->blk_x[k]);
+  }
   if (c->batch_ev) {
     (void)hipEventSynchronize(c->batch_ev);
     (void)hipEventDestroy(c->batch_ev);
@@ -444,7 +495,7 @@ int xc_validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
 
 size_t xc_workspace_bytes(const xc_ctx* c, const xc_setup* s, const xc_station* st) {
   if (validate(const_cast<xc_ctx*>(c), s, st) != XC_OK) return 0;
-  const Layout L = layout_of(s, st, effective_tuning(c, s));
+  const Layout L = layout_of(s, st, effective_tuning(c, s), true);
   return align_up(L.desc_bytes) + L.total;
 }
 
@@ -455,8 +506,12 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
   Prepared p;
   int rc = prepare(c, s, st, workspace, ws_bytes, stream, p);
   if (rc != XC_OK) return rc;
+  if (p.L.nbuf == 2) {
+    rc = ensure_xstream(c);
+    if (rc != XC_OK) return rc;
+  }
   return enqueue_job(c, s, st, out, reinterpret_cast<const DevJob*>(p.desc), p.arena, p.L, p.tu,
-                     stream);
+                     stream, p.L.nbuf == 2 ? c->xstream : nullptr);
 }
 
 int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
@@ -468,7 +523,8 @@ int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
                   (t->xmac_channels_per_wg == 0 || t->xmac_channels_per_wg == 16 ||
                    t->xmac_channels_per_wg == 32 || t->xmac_channels_per_wg == 64) &&
                   t->frames_per_block >= 0 && t->frames_per_block <= kMaxBlockFrames &&
-                  t->xmac_tiles_per_wg >= 0 && t->xmac_tiles_per_wg <= 64;
+                  t->xmac_tiles_per_wg >= 0 && t->xmac_tiles_per_wg <= 64 &&
+                  t->block_overlap >= 0 && t->block_overlap <= 2;
   if (!ok) return fail(c, XC_E_INVAL, "tuning value out of range");
   c->tune = *t;
   return XC_OK;

@@ -53,7 +53,7 @@ XC_BATCH_GRAPH = 1
 class XcTuning(C.Structure):
     _fields_ = [("fstage_waves_per_simd", C.c_int32), ("xmac_frames_per_stage", C.c_int32),
                 ("xmac_channels_per_wg", C.c_int32), ("frames_per_block", C.c_int32),
-                ("xmac_tiles_per_wg", C.c_int32)]
+                ("xmac_tiles_per_wg", C.c_int32), ("block_overlap", C.c_int32)]
 
 
 class XcError(RuntimeError):
@@ -297,7 +297,8 @@ class Correlator:
 
     def set_tuning(self, **kw):
         """Set launch-shape parameters (fstage_waves_per_simd, xmac_frames_per_stage,
-        xmac_channels_per_wg, frames_per_block); unspecified ones keep their value."""
+        xmac_channels_per_wg, frames_per_block, xmac_tiles_per_wg, block_overlap);
+        unspecified ones keep their value."""
         t = XcTuning()
         self._check(self.lib.xc_get_tuning(self.ctx, C.byref(t)))
         for k, v in kw.items():

@@ -46,6 +46,14 @@ int main(void) {
   F(xc_station, frame_ok); F(xc_station, poly_deg); F(xc_station, delay_poly);
   F(xc_station, phase_poly); F(xc_station, poly_t0); F(xc_station, poly_t1);
   F(xc_output, vis); F(xc_output, weight);
+  printf("xc_tuning %zu\nxc_job %zu\nxc_server_stats %zu\n", sizeof(xc_tuning),
+         sizeof(xc_job), sizeof(xc_server_stats));
+  F(xc_tuning, fstage_waves_per_simd); F(xc_tuning, xmac_frames_per_stage);
+  F(xc_tuning, xmac_channels_per_wg); F(xc_tuning, frames_per_block);
+  F(xc_tuning, xmac_tiles_per_wg); F(xc_tuning, block_overlap);
+  F(xc_job, setup); F(xc_job, st); F(xc_job, out);
+  F(xc_server_stats, p50_ms); F(xc_server_stats, completed); F(xc_server_stats, queued);
+  F(xc_server_stats, station_samples_per_s);
   return 0;
 }
 ''')
@@ -54,7 +62,9 @@ int main(void) {
                    check=True)
     out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
                                                        text=True, check=True).stdout.splitlines())
-    py = {"xc_setup": xcorr.XcSetup, "xc_station": xcorr.XcStation, "xc_output": xcorr.XcOutput}
+    py = {"xc_setup": xcorr.XcSetup, "xc_station": xcorr.XcStation, "xc_output": xcorr.XcOutput,
+          "xc_tuning": xcorr.XcTuning, "xc_job": xcorr.XcJob,
+          "xc_server_stats": xcorr.XcServerStats}
     for key, val in out.items():
         if "." in key:
             t, m = key.split(".")
@@ -89,7 +99,7 @@ def test_workspace_bytes_and_validation_on_host():
     s, st, keep = _setup()
     n = lib.xc_workspace_bytes(None, C.byref(s), st)
     assert n > 256 * 2 * 100 * 8          # at least the staged spectra
-    s2, st2, keep2 = _setup(frames_per_block=64)
+    s2, st2, keep2 = _setup(frames_per_block=32)   # two 32-frame block buffers < 100 frames
     assert lib.xc_workspace_bytes(None, C.byref(s2), st2) < n
     for bad in [dict(n_chan=300), dict(n_chan=64), dict(n_streams_recorded=3),
                 dict(n_pols=3), dict(n_stations=0), dict(n_frames=0), dict(frames_per_block=3000),

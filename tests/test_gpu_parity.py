@@ -188,6 +188,28 @@ def test_deterministic_repeat(xc, corr):
         assert torch.equal(corr.correlate(job)[0], a)
 
 
+def test_block_overlap_bit_identical(xc, corr):
+    """F of block b + 1 beside X of block b on a second stream: same visibilities bit for bit,
+    including a ragged last block."""
+    job = configs.small_job(n_stations=4, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=300)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    try:
+        corr.set_tuning(block_overlap=1)
+        ref, w0 = corr.correlate(job, frames_per_block=64)
+        assert rel_l2(ref.cpu().numpy(), V) < TOL
+        corr.set_tuning(block_overlap=2)
+        big = corr.workspace_bytes(job, frames_per_block=64)
+        corr.set_tuning(block_overlap=1)
+        assert big > corr.workspace_bytes(job, frames_per_block=64)   # two block buffers
+        corr.set_tuning(block_overlap=2)
+        for _ in range(2):
+            vis, w = corr.correlate(job, frames_per_block=64)
+            assert torch.equal(vis, ref) and torch.equal(w, w0)
+    finally:
+        corr.set_tuning(block_overlap=0)
+
+
 def test_tuning_variants_bit_identical(xc, corr):
     """Launch-shape variants change speed only: visibilities must be bit-identical."""
     job = configs.small_job(n_stations=5, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=300)
