@@ -15,9 +15,9 @@ struct FGeom {
   static constexpr int E = FftPlan<N>::E;
   static constexpr int G = T >= 256 ? 1 : 256 / T;   // frames per workgroup
   static constexpr int WG = T * G;
-  // Up to N = 4096 the twiddles are staged in LDS (their tables then cost no
-  // registers); larger transforms read them from memory.
-  static constexpr bool tw_in_lds = N <= 4096;
+  // Up to N = 8192 the twiddles are staged in LDS (their tables then cost no
+  // registers); N = 16384 reads them from memory for every input.
+  static constexpr bool tw_in_lds = N <= 8192;
   // G FFT exchange buffers, the 8-entry level table, the twiddle tables
   static constexpr size_t lut_off = (size_t)G * lds_words<N>() * sizeof(float2);
   static constexpr size_t tw_off = lut_off + 8 * sizeof(float);
@@ -47,6 +47,32 @@ __device__ inline void put_spec(void* spec, size_t idx, float2 y, int e) {
   }
 }
 
+// Window words of one station-frame: the payload words holding samples
+// n = t + e T of the frame's window (T is a multiple of 16, so all of a
+// thread's samples share one field offset, returned in sh0).
+template <int N>
+__device__ inline void load_window(const DevJob& J, int s, const DelayRec& r, int t,
+                                   uint32_t (&wv)[FGeom<N>::E], int& sh0) {
+  constexpr int T = FGeom<N>::T, E = FGeom<N>::E;
+  if (r.valid) {
+    const FrameCursor c = make_cursor(J, r.base);
+    const uint32_t* words = J.st[s].words;
+#pragma unroll
+    for (int e = 0; e < E; ++e) wv[e] = *sample_word(J, words, c, t + e * T);
+    sh0 = sample_shift(J, c, t);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) wv[e] = 0u;
+    sh0 = 0;
+  }
+}
+
+// A workgroup holds G frame slots of T threads and works through tasks
+// (station, group of G frames): first task blockIdx.x, then gridDim.x + the
+// next value of the shared counter *ctr (zero at launch), so workgroups that
+// finish early take more.  The delay record and window words of the next task
+// are loaded while the current one is transformed, and the level table and
+// twiddles are set up once per workgroup.
 // W = 0: no occupancy request; W > 0: ask the compiler for W waves per SIMD
 // (caps registers at 512 / W, trading spills for latency hiding).
 // OUT: spectrum element type (kOutF32, kOutF16, kOutF8); for the low-precision
@@ -56,38 +82,21 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
                                amdgpu_waves_per_eu(W > 0 ? W : 1)))
     k_fstage(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
-             void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf) {
+             void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf,
+             unsigned* __restrict__ ctr) {
   constexpr int T = FGeom<N>::T, E = FGeom<N>::E, G = FGeom<N>::G;
+  __shared__ int next_task;
+  // last-pass butterflies per thread: the thread's bins are t + b T + r N/16
+  // (b < BL, r < 16), the kept half r < 8
+  constexpr int BL = E / 16;
+  constexpr int kAnchor = E / 2 < 8 ? E / 2 : 8;   // exact phasor every kAnchor samples
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
-  const int s = blockIdx.y;
-  const int fl = blockIdx.x * G + g;
-  const bool in_blk = fl < nf;
-  DelayRec r;
-  if (in_blk) {
-    r = drec[(size_t)s * nf + fl];
-  } else {
-    r.valid = 0;
-    r.d = 0.0;
-    r.base = 0;
-  }
-  const bool valid = r.valid != 0;
+  const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
+  const int n_groups = (nf + G - 1) / G;
+  const int n_tasks = n_groups * J.n_stations;
 
-  // payload words holding samples n = t + e T of this frame's window; T is a
-  // multiple of 16, so all of a thread's samples share one field offset
-  uint32_t wv[E];
-  int sh0 = 0;
-  if (valid) {
-    const FrameCursor c = make_cursor(J, r.base);
-    const uint32_t* words = J.st[s].words;
-#pragma unroll
-    for (int e = 0; e < E; ++e) wv[e] = *sample_word(J, words, c, t + e * T);
-    sh0 = sample_shift(J, c, t);
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) wv[e] = 0u;
-  }
   float2* lds = lds_all + g * lds_words<N>();
   // 2-bit code -> level (offset binary: -3.3359, -1, +1, +3.3359), and four
   // zeros that an invalid frame's lookups are pointed at
@@ -99,102 +108,178 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   }
   float2* tw_tab = reinterpret_cast<float2*>(lds_b + FGeom<N>::tw_off);
   if constexpr (FGeom<N>::tw_in_lds) tw_lds_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
-  const float* lut_t = lut + (valid ? 0 : 4);
   __syncthreads();
-  const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
 
-  // fractional-delay phasors of this thread's output bins k = t + r N/16:
-  // exp(2 pi i k d / N) = exp(2 pi i t d / N) * exp(2 pi i d / 16)^r
-  float2 fd[8];
-  {
-    const float dd = (float)r.d;
-    fd[0] = phasor_turns((float)t * dd * (1.0f / (float)N));
-    const float2 st = phasor_turns(dd * (1.0f / 16.0f));
-#pragma unroll
-    for (int rr = 1; rr < 8; ++rr) fd[rr] = cmul(fd[rr - 1], st);
-  }
+  // With whole waves per frame (T >= 64) the frame index is wave-uniform: the
+  // delay and phase records then come in through scalar loads, which a wave
+  // does not have to order behind its own outstanding spectrum stores.
+  auto frame_of = [&](int task, int& st, int& fl) {
+    st = task / n_groups;
+    fl = (task - st * n_groups) * G + g;
+    if (T >= 64) fl = __builtin_amdgcn_readfirstlane(fl);
+  };
+  auto record_of = [&](int st, int fl) {
+    DelayRec r;
+    if (fl < nf) {
+      r = drec[(size_t)st * nf + fl];
+    } else {
+      r.valid = 0;
+      r.d = 0.0;
+      r.base = 0;
+    }
+    return r;
+  };
+
+  int task = blockIdx.x;
+  int s = 0, fl = 0;
+  frame_of(task, s, fl);
+  DelayRec r = record_of(s, fl);
+  uint32_t wv[E];
+  int sh0;
+  load_window<N>(J, s, r, t, wv, sh0);
   const double nc0 = (double)(t - N / 2);     // centred index of the thread's first sample
   constexpr double TD = (double)T;
-  // With whole waves per frame (T >= 64) the frame index is wave-uniform: the
-  // phase records then come in through scalar loads, which a wave does not
-  // have to order behind its own outstanding spectrum stores.
-  const int flu = T >= 64 ? __builtin_amdgcn_readfirstlane(fl) : fl;
-  const bool in_blk_u = flu < nf;
 
-  for (int in = 0; in < J.n_inputs; ++in) {
-    const int sb = in / P, p = in - sb * P;
-    const int sh = sh0 + 2 * J.stream_map[in];
-    PhaseRec ph;
-    if (in_blk_u) ph = prec[((size_t)s * n_sb + sb) * nf + flu];
-    else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
-    // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
-    // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
-    // rho: its constant change 2 phi2 T^2), restarted exactly every E/2 samples
-    const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
-    float2 v[E];
-    float2 z = make_float2(1.f, 0.f), w = make_float2(1.f, 0.f);
+  // The next task's words are loaded while this task is transformed, except
+  // for N = 16384 (1024 threads, 128 registers each: no room for them).
+  constexpr bool kPrefetch = N <= 8192;
+  while (task < n_tasks) {
+    if (threadIdx.x == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
+    __syncthreads();
+    const int task_n = next_task;   // rewritten only after the input loop's barriers
+    int s_n = 0, fl_n = nf;
+    if (task_n < n_tasks) frame_of(task_n, s_n, fl_n);
+    const DelayRec r_n = record_of(s_n, fl_n);
+    uint32_t wv_n[kPrefetch ? E : 1];
+    int sh0_n = 0;
+    if constexpr (kPrefetch) load_window<N>(J, s_n, r_n, t, wv_n, sh0_n);
+
+    const bool in_blk = fl < nf;
+    const bool valid = r.valid != 0;
+    const float* lut_t = lut + (valid ? 0 : 4);
+    // fractional-delay phasors of this thread's kept output bins
+    // k = t + b T + r N/16 (b < BL, r < 8): exp(2 pi i k d / N) =
+    // exp(2 pi i (t + b T) d / N) * exp(2 pi i d / 16)^r
+    float2 fd[BL][8];
+    {
+      const float dd = (float)r.d;
+      const float2 st = phasor_turns(dd * (1.0f / 16.0f));
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (e % (E / 2) == 0) {
-        const double nc = nc0 + (double)e * TD;
-        z = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
-        w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
+      for (int b = 0; b < BL; ++b) {
+        fd[b][0] = phasor_turns((float)(t + b * T) * dd * (1.0f / (float)N));
+#pragma unroll
+        for (int rr = 1; rr < 8; ++rr) fd[b][rr] = cmul(fd[b][rr - 1], st);
+      }
+    }
+
+    for (int in = 0; in < J.n_inputs; ++in) {
+      const int sb = in / P, p = in - sb * P;
+      const int sh = sh0 + 2 * J.stream_map[in];
+      PhaseRec ph;
+      if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
+      else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
+      // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
+      // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
+      // rho: its constant change 2 phi2 T^2), restarted exactly every kAnchor samples
+      const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
+      float2 v[E];
+      float2 z = make_float2(1.f, 0.f), w = make_float2(1.f, 0.f);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (e % kAnchor == 0) {
+          const double nc = nc0 + (double)e * TD;
+          z = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
+          w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
+        } else {
+          z = cmul(z, w);
+          w = cmul(w, rho);
+        }
+        const float q = lut_t[(wv[e] >> sh) & 3u];
+        v[e] = make_float2(q * z.x, q * z.y);
+      }
+      if constexpr (FGeom<N>::tw_in_lds) {
+        fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
       } else {
-        z = cmul(z, w);
-        w = cmul(w, rho);
+        // an opaque zero keeps the twiddle loads inside the loop (held across
+        // inputs they would not fit in registers)
+        int zero;
+        __asm__ volatile("s_mov_b32 %0, 0" : "=s"(zero));
+        fft_forward<N>(v, lds, TwGlobal{tw + zero}, t);
       }
-      const float q = lut_t[(wv[e] >> sh) & 3u];
-      v[e] = make_float2(q * z.x, q * z.y);
-    }
-    if constexpr (FGeom<N>::tw_in_lds) fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
-    else fft_forward<N>(v, lds, TwGlobal{tw}, t);
-    if (in_blk) {
-      const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
-      const int8_t* ex = OUT == kOutF32 ? nullptr
-                                        : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
+      if (in_blk) {
+        const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+        const int8_t* ex = OUT == kOutF32 ? nullptr
+                                          : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
 #pragma unroll
-      for (int rr = 0; rr < 8; ++rr) {
-        const int k = t + rr * (N / 16);
-        const float2 y = valid ? cmul(v[rr], fd[rr]) : make_float2(0.f, 0.f);
-        put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+        for (int b = 0; b < BL; ++b)
+#pragma unroll
+          for (int rr = 0; rr < 8; ++rr) {
+            const int k = t + b * T + rr * (N / 16);
+            const float2 y = valid ? cmul(v[b + rr * BL], fd[b][rr]) : make_float2(0.f, 0.f);
+            put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+          }
       }
+      __syncthreads();   // the next input reuses lds
     }
-    __syncthreads();   // the next input reuses lds
+    task = task_n;
+    s = s_n;
+    fl = fl_n;
+    r = r_n;
+    if constexpr (kPrefetch) {
+      sh0 = sh0_n;
+#pragma unroll
+      for (int e = 0; e < E; ++e) wv[e] = wv_n[e];
+    } else {
+      load_window<N>(J, s, r, t, wv, sh0);
+    }
   }
 }
 
 template <int N, int W, int OUT>
 static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* drec,
                             const PhaseRec* prec, const float2* tw, void* spec,
-                            const int8_t* scale_exp, int nf, hipStream_t s) {
+                            const int8_t* scale_exp, int nf, unsigned* ctr, hipStream_t s) {
   using Gm = FGeom<N>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fstage<N, W, OUT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)Gm::lds_bytes);
+  // per device: LDS attribute set, and how many workgroups fill the GPU
+  static int resident[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (!resident[dev]) {
+    e = hipFuncSetAttribute((const void*)k_fstage<N, W, OUT>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::lds_bytes);
+    int per_cu = 0, n_cu = 0;
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fstage<N, W, OUT>, Gm::WG,
+                                                       Gm::lds_bytes);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    resident[dev] = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
   }
-  dim3 grid((nf + Gm::G - 1) / Gm::G, n_stations);
-  hipLaunchKernelGGL((k_fstage<N, W, OUT>), grid, dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec,
-                     tw, spec, scale_exp, nf);
+  const long tasks = (long)((nf + Gm::G - 1) / Gm::G) * n_stations;
+  const int grid = (int)(tasks < resident[dev] ? tasks : resident[dev]);
+  hipLaunchKernelGGL((k_fstage<N, W, OUT>), dim3(grid), dim3(Gm::WG), Gm::lds_bytes, s, job, drec,
+                     prec, tw, spec, scale_exp, nf, ctr);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* drec,
                            const PhaseRec* prec, const float2* tw, void* spec,
-                           const int8_t* scale_exp, int nf, int waves, int out, hipStream_t s) {
+                           const int8_t* scale_exp, int nf, int waves, int out, unsigned* ctr,
+                           hipStream_t s) {
   if (out == kOutF16)
-    return launch_nw<N, 0, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, s);
+    return launch_nw<N, 0, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
   if (out == kOutF8)
-    return launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, s);
+    return launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
   switch (waves) {
-    case 3: return launch_nw<N, 3, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, s);
-    case 4: return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, s);
+    case 3:
+      return launch_nw<N, 3, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
+    case 4:
+      return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     default:
-      return launch_nw<N, 0, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, s);
+      return launch_nw<N, 0, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
   }
 }
 
@@ -207,11 +292,13 @@ bool fstage_supported(int N) {
 
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
                          const PhaseRec* prec, const float2* tw, void* spec,
-                         const int8_t* scale_exp, int nf, int waves, int out, hipStream_t s) {
+                         const int8_t* scale_exp, int nf, int waves, int out, unsigned* ctr,
+                         hipStream_t s) {
+  if (!ctr) return hipErrorInvalidValue;
   switch (N) {
 #define XC_FCASE(NN)                                                                      \
   case NN:                                                                                \
-    return launch_n<NN>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, waves, out, s);
+    return launch_n<NN>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, waves, out, ctr, s);
     XC_FCASE(256) XC_FCASE(512) XC_FCASE(1024) XC_FCASE(2048) XC_FCASE(4096) XC_FCASE(8192)
     XC_FCASE(16384)
 #undef XC_FCASE

@@ -36,9 +36,11 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
 // One thread per (station, block frame).  Writes the integer/fractional delay
 // and validity, and the fringe phase terms of every subband.
 __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
-                         DelayRec* __restrict__ drec, PhaseRec* __restrict__ prec) {
+                         DelayRec* __restrict__ drec, PhaseRec* __restrict__ prec,
+                         unsigned* __restrict__ ctr) {
   const int fl = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
+  if (ctr && fl == 0 && s == 0) *ctr = 0u;
   if (fl >= nf) return;
   const DevJob& J = *job;
   const DevStation& S = J.st[s];
@@ -62,11 +64,11 @@ __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
 }
 
 hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
-                         DelayRec* drec, PhaseRec* prec, hipStream_t s) {
+                         DelayRec* drec, PhaseRec* prec, unsigned* ctr, hipStream_t s) {
   (void)n_subbands;
   const int b = 64;
   dim3 grid((nf + b - 1) / b, n_stations);
-  hipLaunchKernelGGL(k_delays, grid, dim3(b), 0, s, job, f0, nf, drec, prec);
+  hipLaunchKernelGGL(k_delays, grid, dim3(b), 0, s, job, f0, nf, drec, prec, ctr);
   return hipGetLastError();
 }
 

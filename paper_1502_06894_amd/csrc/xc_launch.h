@@ -15,9 +15,10 @@ hipError_t launch_ingest(const uint32_t* words, int64_t n_frames, uint8_t* frame
                          hipStream_t s);
 // Zero n doubles.
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
-// A1: delay and phase records for frames f0 .. f0+nf-1 of every station.
+// A1: delay and phase records for frames f0 .. f0+nf-1 of every station; also
+// zeroes the F stage's task counter *ctr when ctr is not null.
 hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
-                         DelayRec* drec, PhaseRec* prec, hipStream_t s);
+                         DelayRec* drec, PhaseRec* prec, unsigned* ctr, hipStream_t s);
 // A2-A5: spectra [n_subbands][nf][M][n_chan] for the block's frames.
 // Spectrum element types written by the F stage.
 constexpr int kOutF32 = 0;   // float2
@@ -26,9 +27,11 @@ constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, satura
 inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
 
 // waves: occupancy target of the F kernel (0 = compiler's choice, else 3..4; FP32 output only).
+// ctr: task counter, zero at launch (launch_delays clears it), one per concurrent launch.
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
                          const PhaseRec* prec, const float2* tw, void* spec,
-                         const int8_t* scale_exp, int nf, int waves, int out, hipStream_t s);
+                         const int8_t* scale_exp, int nf, int waves, int out, unsigned* ctr,
+                         hipStream_t s);
 // Power-of-two exponents per (subband, input, channel) that bring the mean
 // |Y|^2 of the first nf frames (FP32 spectra [n_sb][nf][M][n_chan]) to
 // target_log2 (i.e. RMS 2^target_log2); 0 when a channel has no power.

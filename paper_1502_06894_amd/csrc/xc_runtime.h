@@ -98,6 +98,7 @@ struct Layout {
   size_t slot_stride = 0;         // double2 elements per slot
   int nbuf = 1;                   // block buffers (2: F of block b+1 beside X of block b)
   size_t drec_bytes = 0, prec_bytes = 0, spec_bytes = 0;   // per block buffer
+  size_t ctr_off = 0;             // F-stage task counter inside each delay-record buffer
 };
 
 ShapeKey shape_key(const xc_setup* s);

@@ -130,7 +130,9 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, b
       off += align_up((size_t)st[i].n_frames_m5b);
     }
   L.nbuf = overlap && tu.block_overlap == 2 && s->n_frames > L.T ? 2 : 1;
-  L.drec_bytes = align_up((size_t)S * L.T * sizeof(DelayRec));
+  // each delay-record buffer ends with the F stage's task counter
+  L.ctr_off = align_up((size_t)S * L.T * sizeof(DelayRec));
+  L.drec_bytes = L.ctr_off + kAlign;
   L.drec = off;
   off += L.nbuf * L.drec_bytes;
   L.prec_bytes = align_up((size_t)S * nsb * L.T * sizeof(PhaseRec));
@@ -249,11 +251,12 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
   if (e != hipSuccess) return hip_fail(c, e, "zero");
   if (L.out != kOutF32) {
     // channel scales from the first frames' FP32 spectra
-    e = launch_delays(dj, S, nsb, 0, L.n_scale, drec, prec, stream);
+    unsigned* ctr0 = reinterpret_cast<unsigned*>(arena + L.drec + L.ctr_off);
+    e = launch_delays(dj, S, nsb, 0, L.n_scale, drec, prec, ctr0, stream);
     if (e == hipSuccess)
       e = timed(c, XC_K_FSTAGE, stream, [&] {
         return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nullptr, L.n_scale, 0, kOutF32,
-                             stream);
+                             ctr0, stream);
       });
     if (e == hipSuccess)
       e = launch_scales(static_cast<const float2*>(spec), nsb, L.n_scale, M, s->n_chan,
@@ -270,19 +273,20 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
     DelayRec* drec_p = reinterpret_cast<DelayRec*>(arena + L.drec + p * L.drec_bytes);
     PhaseRec* prec_p = reinterpret_cast<PhaseRec*>(arena + L.prec + p * L.prec_bytes);
     void* spec_p = arena + L.spec + p * L.spec_bytes;
+    unsigned* ctr_p = reinterpret_cast<unsigned*>(arena + L.drec + p * L.drec_bytes + L.ctr_off);
     hipStream_t xstr = overlap ? xs : stream;
     if (overlap && blk >= 2) {
       e = hipStreamWaitEvent(stream, c->blk_x[p], 0);
       if (e != hipSuccess) return hip_fail(c, e, "block wait");
     }
     e = timed(c, XC_K_DELAYS, stream, [&] {
-      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec_p, prec_p, stream);
+      hipError_t r = launch_delays(dj, S, nsb, f0, nf, drec_p, prec_p, ctr_p, stream);
       return r == hipSuccess ? launch_weights(drec_p, S, nf, wacc, stream) : r;
     });
     if (e != hipSuccess) return hip_fail(c, e, "delays");
     e = timed(c, XC_K_FSTAGE, stream, [&] {
       return launch_fstage(N, dj, S, drec_p, prec_p, c->d_tw, spec_p, sexp, nf,
-                           tu.fstage_waves_per_simd, L.out, stream);
+                           tu.fstage_waves_per_simd, L.out, ctr_p, stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
     if (overlap) {
@@ -589,7 +593,7 @@ int xc_debug_delays(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t*
   std::vector<PhaseRec> hp((size_t)S * nsb * L.T);
   for (int64_t f0 = 0; f0 < F; f0 += L.T) {
     const int nf = (int)((F - f0) < L.T ? (F - f0) : L.T);
-    hipError_t e = launch_delays(dj, S, nsb, f0, nf, drec, prec, stream);
+    hipError_t e = launch_delays(dj, S, nsb, f0, nf, drec, prec, nullptr, stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(hd.data(), drec, sizeof(DelayRec) * S * nf, hipMemcpyDeviceToHost,
                          stream);
@@ -629,7 +633,8 @@ int xc_debug_unpack(xc_ctx* c, const xc_setup* s, const xc_station* st, int32_t 
   PhaseRec* prec = reinterpret_cast<PhaseRec*>(p.arena + p.L.prec);
   float* tmp = reinterpret_cast<float*>(p.arena + p.L.spec);
   const int N = 2 * s->n_chan;
-  hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame, 1, drec, prec, stream);
+  hipError_t e =
+      launch_delays(dj, s->n_stations, s->n_subbands, frame, 1, drec, prec, nullptr, stream);
   if (e == hipSuccess) e = launch_debug_unpack(dj, drec, 1, station, input, 0, tmp, N, stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, tmp, sizeof(float) * N, hipMemcpyDeviceToHost, stream);
@@ -649,10 +654,11 @@ int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t
   const DevJob* dj = reinterpret_cast<const DevJob*>(p.desc);
   DelayRec* drec = reinterpret_cast<DelayRec*>(p.arena + p.L.drec);
   PhaseRec* prec = reinterpret_cast<PhaseRec*>(p.arena + p.L.prec);
-  hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, stream);
+  unsigned* ctr = reinterpret_cast<unsigned*>(p.arena + p.L.drec + p.L.ctr_off);
+  hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, ctr, stream);
   if (e == hipSuccess)
     e = launch_fstage(2 * s->n_chan, dj, s->n_stations, drec, prec, c->d_tw, spectra, nullptr, n,
-                      p.tu.fstage_waves_per_simd, kOutF32, stream);
+                      p.tu.fstage_waves_per_simd, kOutF32, ctr, stream);
   return e == hipSuccess ? XC_OK : hip_fail(c, e, "debug_spectra");
 }
 
