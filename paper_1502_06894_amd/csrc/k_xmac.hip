@@ -240,8 +240,8 @@ __global__ void __launch_bounds__(1024)
 // is hidden.  One wave per 4 x 4 tile, one lane per channel: a wave reads one
 // contiguous 512-byte LDS row per operand, free of bank conflicts.  A frame
 // stage is MP rows of 64 float2; wave w loads rows 2w and 2w + 1 (1 KB, one
-// instruction: LDS address = wave base + 16 * lane), so a wave issues exactly
-// one load per frame or none, and "frame j has landed" is a fixed
+// instruction: LDS address = wave base + 16 * lane), so every wave issues
+// exactly one load per frame and "frame j has landed" is a fixed
 // outstanding-load count.  The ring stages are separate LDS variables so the
 // compiler can tell the in-flight loads apart from the stage being read.
 constexpr int kRing = 8;
@@ -254,18 +254,24 @@ typedef __attribute__((address_space(1))) void glb_void_t;
 constexpr int waitcnt_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 constexpr int waitcnt_vm_lds(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4); }
 
-// One ring step: wait for this wave's load of frame j (and its own LDS reads
-// of frame j - 1), barrier (stage CUR is complete everywhere and the stage of
-// frame j - 1 has been read by every wave), refill that stage NXT with frame
-// j + kRing - 1, multiply stage CUR.
-#define XC_RING_STEP(CUR, NXT)                                                       \
+// One ring step for frame j: wait for this wave's load of frame j + 1 (and
+// its own LDS reads of frame j), barrier (frame j + 1's stage RD is complete
+// everywhere; every wave holds frame j in registers, so stage RF, last used
+// by frame j - 1, is free), refill RF with frame j + kRing - 1, read frame
+// j + 1 from RD into registers NEXT, then multiply frame j from registers CUR:
+// the LDS reads of the next frame are in flight during the multiply.
+#define XC_RING_STEP(RD, RF, CUR_A, CUR_B, NEXT_A, NEXT_B)                            \
   {                                                                                  \
-    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(kRing - 2));                           \
+    __builtin_amdgcn_sched_barrier(0); /* the previous multiply stays before */      \
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(kRing - 3));                           \
     __asm__ volatile("" ::: "memory");                                               \
     __builtin_amdgcn_s_barrier();                                                    \
     __asm__ volatile("" ::: "memory");                                               \
-    ring_load(gsrc + (size_t)min(j + kRing - 1, fz - 1) * fstride4 + loff, NXT + lw * 64);\
-    ring_mac(reinterpret_cast<const float2*>(CUR), gi, gj, lane, acc);               \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+    ring_load(gsrc + (size_t)min(j + kRing - 1, fz - 1) * fstride4 + loff, RF + lw * 64);\
+    ring_read(reinterpret_cast<const float2*>(RD), gi, gj, lane, NEXT_A, NEXT_B);    \
+    __builtin_amdgcn_sched_barrier(0); /* issue the reads before the multiply */     \
+    ring_mac(CUR_A, CUR_B, acc);                                                     \
     ++j;                                                                             \
   }
 
@@ -273,14 +279,18 @@ __device__ __forceinline__ void ring_load(const float4* g, float4* l) {
   __builtin_amdgcn_global_load_lds((glb_void_t*)g, (lds_void_t*)l, 16, 0, 0);
 }
 
-__device__ __forceinline__ void ring_mac(const float2* shb, int gi, int gj, int lane,
-                                         float2 (&acc)[kGroup][kGroup]) {
-  float2 a[kGroup], b[kGroup];
+// This lane's operands of one frame: rows gi*4 + x and gj*4 + x, its channel.
+__device__ __forceinline__ void ring_read(const float2* shb, int gi, int gj, int lane,
+                                          float2 (&a)[kGroup], float2 (&b)[kGroup]) {
 #pragma unroll
   for (int x = 0; x < kGroup; ++x) {
     a[x] = shb[(gi * kGroup + x) * 64 + lane];
     b[x] = shb[(gj * kGroup + x) * 64 + lane];
   }
+}
+
+__device__ __forceinline__ void ring_mac(const float2 (&a)[kGroup], const float2 (&b)[kGroup],
+                                         float2 (&acc)[kGroup][kGroup]) {
 #pragma unroll
   for (int x = 0; x < kGroup; ++x)
 #pragma unroll
@@ -338,7 +348,8 @@ __global__ void __launch_bounds__(1024)
     for (int b = 0; b < kGroup; ++b) acc[a][b] = make_float2(0.f, 0.f);
 
   int j = fa;
-  // frames fa .. fa + kRing - 2 (past the slice: frame fz - 1 again)
+  // frames fa .. fa + kRing - 2 (past the slice: frame fz - 1 again); stage
+  // of frame f: (f - fa) mod kRing
   ring_load(gsrc + (size_t)fa * fstride4 + loff, r0 + lw * 64);
   ring_load(gsrc + (size_t)min(fa + 1, fz - 1) * fstride4 + loff, r1 + lw * 64);
   ring_load(gsrc + (size_t)min(fa + 2, fz - 1) * fstride4 + loff, r2 + lw * 64);
@@ -346,27 +357,37 @@ __global__ void __launch_bounds__(1024)
   ring_load(gsrc + (size_t)min(fa + 4, fz - 1) * fstride4 + loff, r4 + lw * 64);
   ring_load(gsrc + (size_t)min(fa + 5, fz - 1) * fstride4 + loff, r5 + lw * 64);
   ring_load(gsrc + (size_t)min(fa + 6, fz - 1) * fstride4 + loff, r6 + lw * 64);
+  // frame fa into registers A
+  float2 aA[kGroup], bA[kGroup], aB[kGroup], bB[kGroup];
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(kRing - 2));
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+  ring_read(reinterpret_cast<const float2*>(r0), gi, gj, lane, aA, bA);
   // whole rounds of kRing frames, then the rest; no path leads back into the
-  // steps with a different set of loads in flight
+  // steps with a different set of loads in flight.  Frame j is in registers A
+  // at even steps of a round, B at odd ones.
   for (int round = (fz - fa) / kRing; round > 0; --round) {
-    XC_RING_STEP(r0, r7) XC_RING_STEP(r1, r0) XC_RING_STEP(r2, r1) XC_RING_STEP(r3, r2)
-    XC_RING_STEP(r4, r3) XC_RING_STEP(r5, r4) XC_RING_STEP(r6, r5) XC_RING_STEP(r7, r6)
+    XC_RING_STEP(r1, r7, aA, bA, aB, bB) XC_RING_STEP(r2, r0, aB, bB, aA, bA)
+    XC_RING_STEP(r3, r1, aA, bA, aB, bB) XC_RING_STEP(r4, r2, aB, bB, aA, bA)
+    XC_RING_STEP(r5, r3, aA, bA, aB, bB) XC_RING_STEP(r6, r4, aB, bB, aA, bA)
+    XC_RING_STEP(r7, r5, aA, bA, aB, bB) XC_RING_STEP(r0, r6, aB, bB, aA, bA)
   }
   do {
     if (j >= fz) break;
-    XC_RING_STEP(r0, r7)
+    XC_RING_STEP(r1, r7, aA, bA, aB, bB)
     if (j >= fz) break;
-    XC_RING_STEP(r1, r0)
+    XC_RING_STEP(r2, r0, aB, bB, aA, bA)
     if (j >= fz) break;
-    XC_RING_STEP(r2, r1)
+    XC_RING_STEP(r3, r1, aA, bA, aB, bB)
     if (j >= fz) break;
-    XC_RING_STEP(r3, r2)
+    XC_RING_STEP(r4, r2, aB, bB, aA, bA)
     if (j >= fz) break;
-    XC_RING_STEP(r4, r3)
+    XC_RING_STEP(r5, r3, aA, bA, aB, bB)
     if (j >= fz) break;
-    XC_RING_STEP(r5, r4)
+    XC_RING_STEP(r6, r4, aB, bB, aA, bA)
     if (j >= fz) break;
-    XC_RING_STEP(r6, r5)
+    XC_RING_STEP(r7, r5, aA, bA, aB, bB)
   } while (false);
   // no load may still be writing LDS when the workgroup ends
   __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
@@ -390,12 +411,12 @@ __global__ void __launch_bounds__(1024)
 
 static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subbands,
                               const float2* spec, double2* vacc, size_t slot_stride, int nf,
-                              int tpw_req, hipStream_t s) {
+                              int fps_max, int tpw_req, hipStream_t s) {
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
   if (Mp > 32 || n_chan % 64 != 0) return hipErrorInvalidValue;
-  const int n_splits = xmac_splits(nf);
+  const int n_splits = (nf + fps_max - 1) / fps_max;
   const int fps = (nf + n_splits - 1) / n_splits;
   int tiles_per_wg = tpw_req > 0 && tpw_req < 16 ? tpw_req : 16;
   if (tiles_per_wg > ntiles) tiles_per_wg = ntiles;
@@ -420,11 +441,11 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
 
 static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subbands,
                                 const float2* spec, double2* vacc, size_t slot_stride, int nf,
-                                int kc_req, int tpw_req, hipStream_t s) {
+                                int fps_max, int kc_req, int tpw_req, hipStream_t s) {
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
-  const int n_splits = xmac_splits(nf);
+  const int n_splits = (nf + fps_max - 1) / fps_max;
   const int fps = (nf + n_splits - 1) / n_splits;
   int KC = (kc_req == 16 || kc_req == 32 || kc_req == 64) ? kc_req : 64;
   if (KC > n_chan) KC = n_chan;
@@ -451,16 +472,25 @@ static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subb
   return hipGetLastError();
 }
 
-int xmac_splits(int nf) { return (nf + kXmacFramesPerSplit - 1) / kXmacFramesPerSplit; }
+int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands) {
+  // 512-frame slices halve the FP64 slot traffic; taken when the 64-channel
+  // tiles still give at least 512 workgroups (two per compute unit)
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  const int ng = Mp / kGroup;
+  const int ntiles = ng * (ng + 1) / 2;
+  const long zchunks = (ntiles + 15) / 16;
+  const long wgs = (long)(n_chan / 64) * n_subbands * zchunks * ((T + 511) / 512);
+  return wgs >= 512 ? 512 : 256;
+}
 
 template <int FB>
 static hipError_t launch_fb(const DevJob* job, int M, int n_chan, int n_subbands,
                             const float2* spec, double2* vacc, size_t slot_stride, int nf,
-                            int kc_req, int tpw_req, hipStream_t s) {
+                            int fps_max, int kc_req, int tpw_req, hipStream_t s) {
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
-  const int n_splits = xmac_splits(nf);
+  const int n_splits = (nf + fps_max - 1) / fps_max;
   const int fps = (nf + n_splits - 1) / n_splits;
   auto lds_of = [&](int kc) { return 2 * (size_t)FB * Mp * (kc + 2) * sizeof(float2); };
   // widest channel tile that fits 64 KB of LDS and still gives a few
@@ -514,16 +544,18 @@ static hipError_t launch_fb(const DevJob* job, int M, int n_chan, int n_subbands
 }
 
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
-                       const float2* spec, double2* vacc, size_t slot_stride, int nf, int fb,
-                       int kc, int tpw, hipStream_t s) {
+                       const float2* spec, double2* vacc, size_t slot_stride, int nf, int fps,
+                       int fb, int kc, int tpw, hipStream_t s) {
+  if (fps < 1) return hipErrorInvalidValue;
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   if ((fb == 0 || fb == kRing) && Mp <= 32 && (kc == 0 || kc == 64))
-    return launch_ring(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, tpw, s);
+    return launch_ring(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, tpw, s);
   if (fb == 1)
-    return launch_direct(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
+    return launch_direct(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, kc, tpw,
+                         s);
   if (fb == 4)
-    return launch_fb<4>(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
-  return launch_fb<2>(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, kc, tpw, s);
+    return launch_fb<4>(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, kc, tpw, s);
+  return launch_fb<2>(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, kc, tpw, s);
 }
 
 }  // namespace xc

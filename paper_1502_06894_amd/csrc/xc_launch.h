@@ -42,17 +42,18 @@ hipError_t launch_scales(const float2* spec, int n_subbands, int nf, int M, int 
 hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_subbands,
                         const void* spec, const int8_t* scale_exp, double2* vacc,
                         size_t slot_stride, int nf, hipStream_t s);
-// Frames one X workgroup accumulates in FP32 before adding to its FP64 slot.
-constexpr int kXmacFramesPerSplit = 256;
-// Accumulator slots a block of nf frames uses (frames split kXmacFramesPerSplit at a time).
-int xmac_splits(int nf);
+// Frames (at most) one X workgroup accumulates in FP32 before adding to its
+// FP64 slot, for blocks of T frames of a job with M inputs per subband: 512
+// when that still gives the GPU enough workgroups, else 256.  A block of nf
+// frames uses ceil(nf / that) slots.
+int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands);
 // A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
-// (double2), slot_stride elements apart.
-// fb: frames per LDS stage (2 or 4, 0 = default); kc: channel tile (16/32/64, 0 = auto).
-// tpw: 4x4 tiles per workgroup (0 = all that fit in 1024 threads).
+// (double2), slot_stride elements apart; fps: xmac_frames_per_split of the job.
+// fb: staging (8 = LDS ring, 2 or 4 = register-staged stages, 1 = none, 0 = default);
+// kc: channel tile (16/32/64, 0 = auto); tpw: 4x4 tiles per workgroup (0 = all that fit).
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
-                       const float2* spec, double2* vacc, size_t slot_stride, int nf, int fb,
-                       int kc, int tpw, hipStream_t s);
+                       const float2* spec, double2* vacc, size_t slot_stride, int nf, int fps,
+                       int fb, int kc, int tpw, hipStream_t s);
 // Frames of the block valid for both stations of each station pair: wst[si][sj] += count.
 hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* wst,
                           hipStream_t s);

@@ -94,6 +94,7 @@ struct Layout {
   int T = 0;                      // frames per block
   int out = kOutF32;              // spectrum element type written by the F stage
   int n_scale = 0;                // frames of the scale pre-pass (MFMA path)
+  int fps = 256;                  // X stage: frames per FP32 slice (xmac_frames_per_split)
   int n_slots = 1;                // FP64 accumulator slots of the X stage
   size_t slot_stride = 0;         // double2 elements per slot
   int nbuf = 1;                   // block buffers (2: F of block b+1 beside X of block b)

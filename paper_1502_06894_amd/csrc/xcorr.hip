@@ -150,7 +150,8 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, b
   off += L.nbuf * L.spec_bytes;
   L.sexp = off;
   if (L.out != kOutF32) off += align_up((size_t)nsb * M * s->n_chan);
-  L.n_slots = L.out == kOutF32 ? xmac_splits(L.T) : 1;
+  L.fps = xmac_frames_per_split(L.T, M, s->n_chan, nsb);
+  L.n_slots = L.out == kOutF32 ? (L.T + L.fps - 1) / L.fps : 1;
   L.slot_stride = (size_t)nsb * nbl * s->n_chan;
   L.vacc = off;
   off += (size_t)L.n_slots * L.slot_stride * sizeof(double2);   // wacc follows directly
@@ -297,8 +298,8 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
     if (L.out == kOutF32) {
       e = timed(c, XC_K_XMAC, xstr, [&] {
         return launch_xmac(dj, M, s->n_chan, nsb, static_cast<const float2*>(spec_p), vacc,
-                           L.slot_stride, nf, tu.xmac_frames_per_stage, tu.xmac_channels_per_wg,
-                           tu.xmac_tiles_per_wg, xstr);
+                           L.slot_stride, nf, L.fps, tu.xmac_frames_per_stage,
+                           tu.xmac_channels_per_wg, tu.xmac_tiles_per_wg, xstr);
       });
     } else {
       e = timed(c, XC_K_XMFMA, xstr, [&] {
