@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -29,6 +30,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+# FP32 vector FMA without packed-FP32 instructions (this build disables them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (the published 157.3 counts packed FP32)
+FP32_VECTOR_PEAK_TFS = 78.6
 FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published
 
 
@@ -433,12 +437,19 @@ def main():
     alg_bytes = bytes_per_ss * ss * a.steps
     achieved = alg_bytes / (ms_tot * 1e-3) / 1e9
     src_hash = kernel_source_hash(srcs)
+    # the same kernel against the vector-ALU peak: algorithmic flops per
+    # station-sample (FFT 5 log2 N, rotation 2, fractional delay 3; X stage 2 (M + 1))
+    flops_per_ss = {"fstage": 5.0 * math.log2(job.N) + 5.0, "xmac": 2.0 * (job.M + 1)}[dom]
+    alu_achieved = flops_per_ss * ss * a.steps / (ms_tot * 1e-3) / 1e12
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profile(dom, src_hash, 0), "kernel": dom,
             "kernel_ms_per_launch": round(ms_tot / n_launch, 4),
             "algorithmic_bytes_per_launch": round(alg_bytes / n_launch),
-            "bytes_per_station_sample": bytes_per_ss, "source_hash": src_hash}
+            "bytes_per_station_sample": bytes_per_ss, "source_hash": src_hash,
+            "alu": {"achieved": round(alu_achieved, 2), "peak": FP32_VECTOR_PEAK_TFS,
+                    "unit": "TFLOP/s", "frac": round(alu_achieved / FP32_VECTOR_PEAK_TFS, 4),
+                    "flops_per_station_sample": flops_per_ss}}
     kernels = {k: {"ms_per_step": round(ms / a.steps, 3), "launches_per_step": n // a.steps}
                for k, (ms, n) in prof.items() if n}
 
