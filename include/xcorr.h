@@ -262,6 +262,54 @@ void xc_server_destroy(xc_server* srv);
 int xc_autotune(xc_ctx* ctx, const xc_setup* setup, const xc_station* st, const xc_output* out,
                 void* workspace, size_t ws_bytes, void* stream, xc_tuning* best);
 
+/* ---------------------------------------------------------------- fringe search */
+/* Delay-rate fringe search over T stacked sub-integrations: the search behind
+ * the paper's first-fringe result (a single peak in residual delay and rate
+ * inside a fringe-search window) and its wide search windows (section 2).
+ * Per subband and baseline, with V_t[k] the visibility of sub-integration t,
+ * channel k:
+ *   F_t[d]  = sum_{k < n_chan} V_t[k] exp(-2 pi i k d / D)   (zero-padded to D)
+ *   G[r, d] = sum_{t < T}      F_t[d] exp(-2 pi i t r / R)   (zero-padded to R)
+ * Bins are signed, d in [-D/2, D/2) and r in [-R/2, R/2); the peak is the
+ * largest |G| with |d| <= delay_win and |r| <= rate_win (0 = the whole axis),
+ * ties going to the smallest r D + d of the unsigned bins; a parabola through
+ * |G| at the peak and its two cyclic neighbours along each axis gives sub-bin
+ * offsets.  FP32 arithmetic. */
+typedef struct {
+  int32_t n_subints;           /* T, 1..256 */
+  int32_t n_subbands;          /* >= 1 */
+  int32_t n_baselines;         /* >= 1 (e.g. M(M+1)/2 of a correlate output) */
+  int32_t n_chan;              /* >= 1 */
+  int32_t delay_len;           /* D: power of two, 256..16384, >= n_chan */
+  int32_t rate_len;            /* R: power of two, T..1024 */
+  int32_t delay_win;           /* search half-width in delay bins, 0 = whole axis */
+  int32_t rate_win;            /* search half-width in rate bins, 0 = whole axis */
+  double  chan_width_hz;       /* channel spacing dnu > 0 */
+  double  t_int_s;             /* sub-integration spacing > 0 */
+} xc_fringe_setup;
+
+typedef struct {
+  int32_t delay_bin;           /* signed peak bins */
+  int32_t rate_bin;
+  float   amp;                 /* |G| / (n_chan T): a unit-modulus fringe gives 1 */
+  float   phase;               /* arg G at the peak, radians */
+  float   delay_off;           /* parabolic sub-bin offsets */
+  float   rate_off;
+  double  delay_s;             /* (delay_bin + delay_off) / (D dnu) */
+  double  rate_hz;             /* (rate_bin + rate_off) / (R t_int) */
+} xc_fringe_peak;
+
+/* Device workspace xc_fringe_search needs (0 if the setup is invalid). */
+size_t xc_fringe_workspace_bytes(const xc_fringe_setup* fs);
+/* vis: device complex float [T][n_subbands][n_baselines][n_chan] (for example
+ * T correlate outputs, stacked); peaks: device xc_fringe_peak
+ * [n_subbands][n_baselines]; map: NULL, or device complex float
+ * [n_subbands][n_baselines][R][D] receiving G.  The caller owns every buffer.
+ * Async on `stream`.  Errors: XC_E_INVAL (setup out of range or a NULL buffer),
+ * XC_E_NOMEM (workspace smaller than xc_fringe_workspace_bytes), XC_E_HIP. */
+int xc_fringe_search(xc_ctx* ctx, const xc_fringe_setup* fs, const void* vis, void* peaks,
+                     void* map, void* workspace, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- kernel timing */
 /* Kernel kinds for xc_profile_end. */
 #define XC_K_INGEST    0
@@ -271,7 +319,8 @@ int xc_autotune(xc_ctx* ctx, const xc_setup* setup, const xc_station* st, const 
 #define XC_K_XMFMA     4
 #define XC_K_FINALISE  5
 #define XC_K_ZERO      6
-#define XC_NKINDS      7
+#define XC_K_FRINGE    7
+#define XC_NKINDS      8
 
 /* Start recording a HIP event pair around every kernel launch of this context
  * (on the launch's own stream), for at most max_launches launches. */

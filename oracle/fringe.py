@@ -61,8 +61,8 @@ def delay_rate_map(V: np.ndarray, delay_len: int, rate_len: int) -> np.ndarray:
 
 
 def signed(b: int, n: int) -> int:
-    """F3."""
-    return b - n if b >= n // 2 else b
+    """F3 (a one-point axis has the single bin 0)."""
+    return b - n if b >= (n + 1) // 2 else b
 
 
 def _window_mask(R: int, D: int, delay_win: int, rate_win: int) -> np.ndarray:

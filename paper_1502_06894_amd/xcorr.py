@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxcorr.s
 XC_OK, XC_E_INVAL, XC_E_RANGE, XC_E_NOMEM, XC_E_HIP, XC_E_CANCELLED, XC_E_TIMEOUT = (
     0, -1, -2, -3, -4, -5, -6)
 XC_FP32, XC_FP16_MFMA, XC_FP8_MFMA = 0, 1, 2
-KERNEL_KINDS = ["ingest", "delays", "fstage", "xmac", "xmfma", "finalise", "zero"]
+KERNEL_KINDS = ["ingest", "delays", "fstage", "xmac", "xmfma", "finalise", "zero", "fringe"]
 PRECISIONS = {"fp32": XC_FP32, "fp16": XC_FP16_MFMA, "fp8": XC_FP8_MFMA}
 
 
@@ -54,6 +54,25 @@ class XcTuning(C.Structure):
     _fields_ = [("fstage_waves_per_simd", C.c_int32), ("xmac_frames_per_stage", C.c_int32),
                 ("xmac_channels_per_wg", C.c_int32), ("frames_per_block", C.c_int32),
                 ("xmac_tiles_per_wg", C.c_int32), ("block_overlap", C.c_int32)]
+
+
+class XcFringeSetup(C.Structure):
+    _fields_ = [("n_subints", C.c_int32), ("n_subbands", C.c_int32), ("n_baselines", C.c_int32),
+                ("n_chan", C.c_int32), ("delay_len", C.c_int32), ("rate_len", C.c_int32),
+                ("delay_win", C.c_int32), ("rate_win", C.c_int32),
+                ("chan_width_hz", C.c_double), ("t_int_s", C.c_double)]
+
+
+class XcFringePeak(C.Structure):
+    _fields_ = [("delay_bin", C.c_int32), ("rate_bin", C.c_int32), ("amp", C.c_float),
+                ("phase", C.c_float), ("delay_off", C.c_float), ("rate_off", C.c_float),
+                ("delay_s", C.c_double), ("rate_hz", C.c_double)]
+
+
+# numpy view of an xc_fringe_peak array
+FRINGE_PEAK_DTYPE = np.dtype([("delay_bin", "<i4"), ("rate_bin", "<i4"), ("amp", "<f4"),
+                              ("phase", "<f4"), ("delay_off", "<f4"), ("rate_off", "<f4"),
+                              ("delay_s", "<f8"), ("rate_hz", "<f8")])
 
 
 class XcError(RuntimeError):
@@ -97,6 +116,9 @@ def load_library() -> C.CDLL:
                                       C.POINTER(XcTuning)]),
             "xc_set_tuning": (C.c_int, [P, C.POINTER(XcTuning)]),
             "xc_get_tuning": (C.c_int, [P, C.POINTER(XcTuning)]),
+            "xc_fringe_workspace_bytes": (C.c_size_t, [C.POINTER(XcFringeSetup)]),
+            "xc_fringe_search": (C.c_int, [P, C.POINTER(XcFringeSetup), P, P, P, P, C.c_size_t,
+                                           P]),
             "xc_profile_begin": (C.c_int, [P, C.c_int32]),
             "xc_profile_end": (C.c_int, [P, P, P]),
         }
@@ -309,6 +331,38 @@ class Correlator:
         t = XcTuning()
         self._check(self.lib.xc_get_tuning(self.ctx, C.byref(t)))
         return {f: getattr(t, f) for f, _ in XcTuning._fields_}
+
+    def fringe_search(self, vis: torch.Tensor, delay_len: int, rate_len: int,
+                      chan_width_hz: float, t_int_s: float, delay_win: int = 0,
+                      rate_win: int = 0, want_map: bool = False, workspace=None, stream=None):
+        """Delay-rate fringe search (xc_fringe_search) over vis, a device complex64
+        tensor [T, n_subbands, n_baselines, n_chan].  Returns (peaks, map): peaks a
+        numpy structured array [n_subbands, n_baselines] (FRINGE_PEAK_DTYPE), map the
+        device complex64 tensor [n_subbands, n_baselines, rate_len, delay_len] or None."""
+        if vis.dtype != torch.complex64 or vis.dim() != 4 or not vis.is_cuda:
+            raise XcError(XC_E_INVAL, "vis must be a 4-d complex64 device tensor")
+        vis = vis.contiguous()
+        T, nsb, nbl, nch = vis.shape
+        fs = XcFringeSetup(T, nsb, nbl, nch, int(delay_len), int(rate_len), int(delay_win),
+                           int(rate_win), float(chan_width_hz), float(t_int_s))
+        need = int(self.lib.xc_fringe_workspace_bytes(C.byref(fs)))
+        if need == 0:
+            # let the library name what is wrong
+            self._check(self.lib.xc_fringe_search(self.ctx, C.byref(fs), None, None, None, None,
+                                                  0, None))
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=vis.device)
+        peaks = torch.empty((nsb, nbl, FRINGE_PEAK_DTYPE.itemsize), dtype=torch.uint8,
+                            device=vis.device)
+        gmap = (torch.empty((nsb, nbl, rate_len, delay_len), dtype=torch.complex64,
+                            device=vis.device) if want_map else None)
+        self._check(self.lib.xc_fringe_search(
+            self.ctx, C.byref(fs), vis.data_ptr(), peaks.data_ptr(),
+            gmap.data_ptr() if gmap is not None else None, workspace.data_ptr(),
+            workspace.numel(), _stream_ptr(stream)))
+        (stream or torch.cuda.current_stream()).synchronize()
+        out = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=FRINGE_PEAK_DTYPE)
+        return out.reshape(nsb, nbl), gmap
 
     def profile_begin(self, max_launches: int = 8192):
         """Time every kernel launch of this context with HIP events on its stream."""

@@ -54,6 +54,12 @@ int main(void) {
   F(xc_job, setup); F(xc_job, st); F(xc_job, out);
   F(xc_server_stats, p50_ms); F(xc_server_stats, completed); F(xc_server_stats, queued);
   F(xc_server_stats, station_samples_per_s);
+  printf("xc_fringe_setup %zu\nxc_fringe_peak %zu\n", sizeof(xc_fringe_setup),
+         sizeof(xc_fringe_peak));
+  F(xc_fringe_setup, n_subints); F(xc_fringe_setup, rate_win); F(xc_fringe_setup, chan_width_hz);
+  F(xc_fringe_setup, t_int_s);
+  F(xc_fringe_peak, delay_bin); F(xc_fringe_peak, amp); F(xc_fringe_peak, rate_off);
+  F(xc_fringe_peak, delay_s); F(xc_fringe_peak, rate_hz);
   return 0;
 }
 ''')
@@ -64,7 +70,8 @@ int main(void) {
                                                        text=True, check=True).stdout.splitlines())
     py = {"xc_setup": xcorr.XcSetup, "xc_station": xcorr.XcStation, "xc_output": xcorr.XcOutput,
           "xc_tuning": xcorr.XcTuning, "xc_job": xcorr.XcJob,
-          "xc_server_stats": xcorr.XcServerStats}
+          "xc_server_stats": xcorr.XcServerStats, "xc_fringe_setup": xcorr.XcFringeSetup,
+          "xc_fringe_peak": xcorr.XcFringePeak}
     for key, val in out.items():
         if "." in key:
             t, m = key.split(".")
@@ -109,6 +116,23 @@ def test_workspace_bytes_and_validation_on_host():
     # sub-integration outside the polynomial span
     s3, st3, k3 = _setup(sub_start=200 * 32_000_000)
     assert lib.xc_workspace_bytes(None, C.byref(s3), st3) == 0
+
+
+def test_fringe_workspace_and_validation_on_host():
+    lib = xcorr.load_library()
+
+    def fs(**kw):
+        d = dict(n_subints=8, n_subbands=2, n_baselines=3, n_chan=128, delay_len=256, rate_len=16,
+                 delay_win=0, rate_win=0, chan_width_hz=1e4, t_int_s=0.5)
+        d.update(kw)
+        return xcorr.XcFringeSetup(**d)
+    n = lib.xc_fringe_workspace_bytes(C.byref(fs()))
+    assert n >= 2 * 3 * 8 * 256 * 8                       # the delay-transform rows
+    assert xcorr.FRINGE_PEAK_DTYPE.itemsize == C.sizeof(xcorr.XcFringePeak)
+    for bad in [dict(delay_len=300), dict(delay_len=128), dict(n_chan=512), dict(rate_len=4),
+                dict(rate_len=2048), dict(n_subints=0), dict(n_subints=300, rate_len=512),
+                dict(t_int_s=0.0), dict(delay_win=-1)]:
+        assert lib.xc_fringe_workspace_bytes(C.byref(fs(**bad))) == 0, bad
 
 
 def test_create_without_gpu_fails_cleanly():
