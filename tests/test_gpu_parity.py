@@ -138,6 +138,29 @@ def test_visibility_parity(xc, corr, name, kw, fpb):
     assert rel_l2(vis, V) < TOL, name
 
 
+@pytest.mark.parametrize("tau2", [3e-8, 1.6e-3])
+def test_perigee_acceleration_parity(xc, corr, tau2):
+    """A space station near perigee: delay rate 3e-5 s/s and delay acceleration tau''
+    of 3e-8 s/s^2 (gravity-class) and 1.6e-3 s/s^2 (a stress case whose quadratic
+    fringe phase reaches ~0.1 rad across an N = 4096 frame): the per-frame phase
+    Taylor terms and the second-order phasor recurrence match the oracle's per-sample
+    long-double phase."""
+    from synth import shape
+    fs, n_chan, t0 = configs.FS_16MHZ, 2048, configs.SUB_START_S
+    ground = [0.011, -2e-6, 0.0]
+    # space(t) = 0.08 + 3e-5 (t - t0) + tau2 / 2 (t - t0)^2, expanded about t = 0
+    space = [0.08 - 3e-5 * t0 + 0.5 * tau2 * t0 * t0, 3e-5 - tau2 * t0, 0.5 * tau2]
+    job = shape.build_job(n_stations=2, n_subbands=2, n_pols=1, n_chan=n_chan, C=2, fs=fs,
+                          lo_hz=[configs.LO0_HZ, configs.LO0_HZ + 16e6],
+                          sub_start=int(t0 * fs), n_frames=40, delay_polys=[ground, space],
+                          shifts=[0, 0], phase_zero=False, seed=91, margin=4096)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    vis, w = corr.correlate(job)
+    assert np.array_equal(w.cpu().numpy(), W.astype(np.float32))
+    assert rel_l2(vis.cpu().numpy(), V) < TOL
+
+
 def test_bad_frames_and_out_of_buffer(xc, corr):
     job = configs.small_job(n_stations=3, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=400,
                             realistic=False, seed=5)
