@@ -12,6 +12,7 @@ Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py --workload c3        # 64 uneven jobs: batch (lanes + hipGraph) vs per-job loop
   python bench.py --workload c5        # Poisson request trace through the server
   python bench.py --workload fringe    # delay-rate fringe search over a C2-shaped scan
+  python bench.py --workload feed      # feed-angle correction over a C2-shaped scan
   python bench.py --calibrate-copy     # plain device copy of known size, for counter scaling
   python bench.py --rocpd-summary DB   # per-kernel table from a rocprofv3 database
 """
@@ -413,6 +414,45 @@ def run_fringe(a):
     }
 
 
+def run_feed(a):
+    """Feed-angle correction, in place, over a C2-shaped scan of dual-pol products:
+    64 sub-integrations x 8 subbands x 210 products x 1024 channels, circular feeds."""
+    import torch
+    from paper_1502_06894_amd import xcorr
+    T, n_sb, S, n_chan = 64, 8, 10, 1024
+    nbl = 2 * S * (2 * S + 1) // 2
+    g = torch.Generator(device="cuda").manual_seed(1502068947)
+    V = torch.randn((T, n_sb, nbl, n_chan), dtype=torch.complex64, device="cuda", generator=g)
+    ang = torch.rand((T, S), dtype=torch.float64, device="cuda", generator=g) * 6.28 - 3.14
+    corr = xcorr.Correlator(0)
+    for _ in range(a.warmup):
+        corr.feed_correct(V, ang, xcorr.XC_FEED_CIRCULAR)
+    corr.profile_begin(4 * a.steps + 8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        corr.feed_correct(V, ang, xcorr.XC_FEED_CIRCULAR)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    ms_k = corr.profile_end()["feed"][0] / max(1, a.steps)
+    nbytes = 2.0 * V.numel() * 8                      # read and write every product
+    gbs = nbytes / (ms_k * 1e-3) / 1e9
+    log(f"feed correction: {dt * 1e3:.3f} ms per scan, kernel {ms_k:.3f} ms, {gbs:.0f} GB/s")
+    return {
+        "metric": "feed-corrected products/s", "value": round(V.numel() / dt / 1e9, 2),
+        "unit": "G products/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "feed-angle correction: C2-shaped scan, 64 sub-integrations x 8 "
+                               "subbands x 210 dual-pol products x 1024 channels, circular feeds"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "feed", "kernel_ms_per_launch": round(ms_k, 4),
+                     "algorithmic_bytes_per_launch": nbytes},
+        "cpu_baseline": None,
+    }
+
+
 def ctypes_byref(x):
     import ctypes
     return ctypes.byref(x)
@@ -451,8 +491,9 @@ def main():
         calibrate_copy()
         return
 
-    if a.workload in ("c3", "c4", "c5", "fringe"):
-        res = {"c3": run_c3, "c4": run_c4, "c5": run_c5, "fringe": run_fringe}[a.workload](a)
+    if a.workload in ("c3", "c4", "c5", "fringe", "feed"):
+        res = {"c3": run_c3, "c4": run_c4, "c5": run_c5, "fringe": run_fringe,
+               "feed": run_feed}[a.workload](a)
         print(json.dumps(res), flush=True)
         return
 

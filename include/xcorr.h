@@ -310,6 +310,34 @@ size_t xc_fringe_workspace_bytes(const xc_fringe_setup* fs);
 int xc_fringe_search(xc_ctx* ctx, const xc_fringe_setup* fs, const void* vis, void* peaks,
                      void* map, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- feed-angle correction */
+/* The equivalent of the parallactic-angle correction for dual-polarisation
+ * products (the paper lists it for the spaceborne antenna, computed from the
+ * spacecraft orientation in its telemetry; section 2).  The angles are inputs.
+ * A feed turned by chi gives, for linear feeds, X' = X cos chi + Y sin chi,
+ * Y' = -X sin chi + Y cos chi; for circular feeds R' = exp(-i chi) R,
+ * L' = exp(+i chi) L.  The correction restores the unturned feeds' products:
+ * circular V_ij exp(+i (s_p chi_a - s_q chi_b)) with s_R = +1, s_L = -1;
+ * linear, per station pair, V <- Rot(chi_a)^T V Rot(chi_b),
+ * Rot = [[cos, sin], [-sin, cos]].  FP32 products, FP64 angles. */
+#define XC_FEED_CIRCULAR 0      /* pol 0 = R, pol 1 = L */
+#define XC_FEED_LINEAR   1      /* pol 0 = X, pol 1 = Y */
+
+typedef struct {
+  int32_t n_subints;           /* T >= 1 */
+  int32_t n_subbands;          /* >= 1 */
+  int32_t n_stations;          /* S >= 1: products of M = 2 S inputs, i = 2 s + p */
+  int32_t n_chan;              /* >= 1 */
+  int32_t feed;                /* XC_FEED_CIRCULAR or XC_FEED_LINEAR */
+} xc_feed_setup;
+
+/* In place on vis: device complex float [T][n_subbands][M(M+1)/2][n_chan]
+ * (packed upper triangle i <= j, as xc_correlate_subint writes it, stacked over
+ * T sub-integrations); angles: device double [T][S], radians.  Async on
+ * `stream`.  Errors: XC_E_INVAL (setup out of range or a NULL pointer), XC_E_HIP. */
+int xc_feed_correct(xc_ctx* ctx, const xc_feed_setup* fs, void* vis, const double* angles,
+                    void* stream);
+
 /* ---------------------------------------------------------------- kernel timing */
 /* Kernel kinds for xc_profile_end. */
 #define XC_K_INGEST    0
@@ -320,7 +348,8 @@ int xc_fringe_search(xc_ctx* ctx, const xc_fringe_setup* fs, const void* vis, vo
 #define XC_K_FINALISE  5
 #define XC_K_ZERO      6
 #define XC_K_FRINGE    7
-#define XC_NKINDS      8
+#define XC_K_FEED      8
+#define XC_NKINDS      9
 
 /* Start recording a HIP event pair around every kernel launch of this context
  * (on the launch's own stream), for at most max_launches launches. */

@@ -18,7 +18,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxcorr.s
 XC_OK, XC_E_INVAL, XC_E_RANGE, XC_E_NOMEM, XC_E_HIP, XC_E_CANCELLED, XC_E_TIMEOUT = (
     0, -1, -2, -3, -4, -5, -6)
 XC_FP32, XC_FP16_MFMA, XC_FP8_MFMA = 0, 1, 2
-KERNEL_KINDS = ["ingest", "delays", "fstage", "xmac", "xmfma", "finalise", "zero", "fringe"]
+KERNEL_KINDS = ["ingest", "delays", "fstage", "xmac", "xmfma", "finalise", "zero", "fringe",
+                "feed"]
 PRECISIONS = {"fp32": XC_FP32, "fp16": XC_FP16_MFMA, "fp8": XC_FP8_MFMA}
 
 
@@ -75,6 +76,14 @@ FRINGE_PEAK_DTYPE = np.dtype([("delay_bin", "<i4"), ("rate_bin", "<i4"), ("amp",
                               ("delay_s", "<f8"), ("rate_hz", "<f8")])
 
 
+class XcFeedSetup(C.Structure):
+    _fields_ = [("n_subints", C.c_int32), ("n_subbands", C.c_int32), ("n_stations", C.c_int32),
+                ("n_chan", C.c_int32), ("feed", C.c_int32)]
+
+
+XC_FEED_CIRCULAR, XC_FEED_LINEAR = 0, 1
+
+
 class XcError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"xcorr error {code}: {msg}")
@@ -119,6 +128,7 @@ def load_library() -> C.CDLL:
             "xc_fringe_workspace_bytes": (C.c_size_t, [C.POINTER(XcFringeSetup)]),
             "xc_fringe_search": (C.c_int, [P, C.POINTER(XcFringeSetup), P, P, P, P, C.c_size_t,
                                            P]),
+            "xc_feed_correct": (C.c_int, [P, C.POINTER(XcFeedSetup), P, P, P]),
             "xc_profile_begin": (C.c_int, [P, C.c_int32]),
             "xc_profile_end": (C.c_int, [P, P, P]),
         }
@@ -363,6 +373,20 @@ class Correlator:
         (stream or torch.cuda.current_stream()).synchronize()
         out = np.frombuffer(peaks.cpu().numpy().tobytes(), dtype=FRINGE_PEAK_DTYPE)
         return out.reshape(nsb, nbl), gmap
+
+    def feed_correct(self, vis: torch.Tensor, angles: torch.Tensor, feed: int, stream=None):
+        """Feed-angle correction (xc_feed_correct), in place: vis a device complex64
+        tensor [T, n_subbands, M(M+1)/2, n_chan] with M = 2 S, angles a device float64
+        tensor [T, S] in radians."""
+        if vis.dtype != torch.complex64 or vis.dim() != 4 or not vis.is_contiguous():
+            raise XcError(XC_E_INVAL, "vis must be a contiguous 4-d complex64 device tensor")
+        angles = angles.to(device=vis.device, dtype=torch.float64).contiguous()
+        T, nsb, nbl, nch = vis.shape
+        S = angles.shape[1]
+        fs = XcFeedSetup(T, nsb, S, nch, int(feed))
+        self._check(self.lib.xc_feed_correct(self.ctx, C.byref(fs), vis.data_ptr(),
+                                             angles.data_ptr(), _stream_ptr(stream)))
+        return vis
 
     def profile_begin(self, max_launches: int = 8192):
         """Time every kernel launch of this context with HIP events on its stream."""
