@@ -73,13 +73,13 @@ __device__ inline void load_window(const DevJob& J, int s, const DelayRec& r, in
 // finish early take more.  The delay record and window words of the next task
 // are loaded while the current one is transformed, and the level table and
 // twiddles are set up once per workgroup.
-// W = 0: no occupancy request; W > 0: ask the compiler for W waves per SIMD
-// (caps registers at 512 / W, trading spills for latency hiding).
+// W = 0: default; W = 2: the pols of a subband share their fringe phasors;
+// W = 3, 4: ask the compiler for W waves per SIMD (caps registers at 512 / W).
 // OUT: spectrum element type (kOutF32, kOutF16, kOutF8); for the low-precision
 // outputs `scale_exp` [n_sb][M][n_chan] holds the power-of-two exponents.
 template <int N, int W, int OUT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
-                               amdgpu_waves_per_eu(W > 0 ? W : 1)))
+                               amdgpu_waves_per_eu(W > 2 ? W : 1)))
     k_fstage(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
              void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf,
@@ -90,6 +90,9 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // (b < BL, r < 16), the kept half r < 8
   constexpr int BL = E / 16;
   constexpr int kAnchor = E / 2 < 8 ? E / 2 : 8;   // exact phasor every kAnchor samples
+  // W = 2: a subband's pols share one set of fringe phasors (both see the same
+  // fringe phase), held in registers from the first pol to the second
+  constexpr bool kShare = W == 2;
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
@@ -172,30 +175,37 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
       }
     }
 
+    // the fringe phasors of a subband, kept for its second pol when kShare
+    float2 zs[E];
     for (int in = 0; in < J.n_inputs; ++in) {
       const int sb = in / P, p = in - sb * P;
       const int sh = sh0 + 2 * J.stream_map[in];
-      PhaseRec ph;
-      if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
-      else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
-      // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
-      // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
-      // rho: its constant change 2 phi2 T^2), restarted exactly every kAnchor samples
-      const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
+      if (!kShare || p == 0) {
+        PhaseRec ph;
+        if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
+        else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
+        // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
+        // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
+        // rho: its constant change 2 phi2 T^2), restarted exactly every kAnchor samples
+        const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
+        float2 w = make_float2(1.f, 0.f);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (e % kAnchor == 0) {
+            const double nc = nc0 + (double)e * TD;
+            zs[e] = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
+            w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
+          } else {
+            zs[e] = cmul(zs[e - 1], w);
+            w = cmul(w, rho);
+          }
+        }
+      }
       float2 v[E];
-      float2 z = make_float2(1.f, 0.f), w = make_float2(1.f, 0.f);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        if (e % kAnchor == 0) {
-          const double nc = nc0 + (double)e * TD;
-          z = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
-          w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
-        } else {
-          z = cmul(z, w);
-          w = cmul(w, rho);
-        }
         const float q = lut_t[(wv[e] >> sh) & 3u];
-        v[e] = make_float2(q * z.x, q * z.y);
+        v[e] = make_float2(q * zs[e].x, q * zs[e].y);
       }
       if constexpr (FGeom<N>::tw_in_lds) {
         fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
@@ -274,6 +284,8 @@ static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* dr
   if (out == kOutF8)
     return launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
   switch (waves) {
+    case 2:
+      return launch_nw<N, 2, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     case 3:
       return launch_nw<N, 3, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     case 4:
