@@ -168,7 +168,10 @@ int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
  * frames_per_block, which changes FP32 summation order (results stay within
  * the FP32 path's tolerance). */
 typedef struct {
-  int32_t fstage_waves_per_simd;   /* F-stage occupancy target: 0, 1, 2, 3 or 4 */
+  int32_t fstage_waves_per_simd;   /* F-stage variant: 0 or 1 = default; 2 = the pols of a
+                                      subband share their fringe phasors (fewer operations,
+                                      more registers); 3 or 4 = at least that many waves per
+                                      SIMD requested (fewer registers) */
   int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
                                       stages filled by direct memory-to-LDS loads (64-channel
                                       tiles, at most 32 inputs per subband; the default where
