@@ -476,7 +476,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=8, help="c3/c5: concurrent lanes")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: mean arrival rate (1/s)")
-    ap.add_argument("--max-log2-chan", type=int, default=13, help="c5: largest log2(channels)")
+    ap.add_argument("--max-log2-chan", type=int, default=14, help="c5: largest log2(channels)")
     ap.add_argument("--budget-gb", type=int, default=96, help="c5: server HBM budget (GiB)")
     a = ap.parse_args()
     if a.rocpd_summary:

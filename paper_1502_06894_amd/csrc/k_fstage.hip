@@ -295,17 +295,155 @@ static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* dr
   }
 }
 
+// ---------------------------------------------------------------- N = 32768
+// Too large for one workgroup's LDS, N = 32768 = 16 x 2048 runs as a
+// four-step FFT through a scratch buffer Z.  Sample n = n2 + 2048 n1
+// (n1 < 16, n2 < 2048); bin k = k1 + 16 k2.
+//   A: per (station, frame, input) and n2: unpack, fringe rotation, the
+//      16-point DFT over n1, times exp(-2 pi i n2 k1 / N), into Z row k1;
+//   B: per row k1, the 2048-point FFT over n2 gives bins k1 + 16 k2; the kept
+//      half (k2 < 1024) is multiplied by the fractional-delay phasor and stored.
+constexpr int kBigN = 32768, kBigN2 = 2048, kBigChunk = 256;
+
+__global__ void __launch_bounds__(kBigChunk)
+    k_fbig_a(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
+             const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
+             float2* __restrict__ Z, int nf) {
+  const DevJob& J = *job;
+  const int n2 = blockIdx.x * kBigChunk + threadIdx.x;
+  const int fl = blockIdx.y, s = blockIdx.z;
+  const DelayRec r = drec[(size_t)s * nf + fl];
+  const bool valid = r.valid != 0;
+  uint32_t wv[16];
+  int sh0 = 0;
+  if (valid) {
+    const FrameCursor c = make_cursor(J, r.base);
+    const uint32_t* words = J.st[s].words;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) wv[e] = *sample_word(J, words, c, n2 + e * kBigN2);
+    sh0 = sample_shift(J, c, n2);
+  }
+  const int P = J.n_pols, n_sb = J.n_subbands;
+  const double nc0 = (double)(n2 - kBigN / 2);
+  constexpr double TD = (double)kBigN2;
+  float2* zrow0 = Z + (((size_t)s * nf + fl) * J.n_inputs) * kBigN;
+  for (int in = 0; in < J.n_inputs; ++in) {
+    const int sb = in / P;
+    const int sh = sh0 + 2 * J.stream_map[in];
+    const PhaseRec ph = prec[((size_t)s * n_sb + sb) * nf + fl];
+    const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
+    float2 v[16];
+    float2 z = make_float2(1.f, 0.f), w = make_float2(1.f, 0.f);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      if (e % 8 == 0) {
+        const double nc = nc0 + (double)e * TD;
+        z = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
+        w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
+      } else {
+        z = cmul(z, w);
+        w = cmul(w, rho);
+      }
+      const float q = valid ? level_of((wv[e] >> sh) & 3u) : 0.0f;
+      v[e] = make_float2(q * z.x, q * z.y);
+    }
+    Dft<16>::run(v);
+    float2* zr = zrow0 + (size_t)in * kBigN;
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) {
+      const float2 y = k1 == 0 ? v[0] : cmul(v[k1], tw[n2 * k1]);   // n2 k1 < kTwiddleN
+      zr[k1 * kBigN2 + n2] = y;
+    }
+  }
+}
+
+template <int OUT>
+__global__ void __launch_bounds__(256)
+    k_fbig_b(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
+             const float2* __restrict__ tw, const float2* __restrict__ Z,
+             void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf) {
+  constexpr int T = FftPlan<kBigN2>::T, E = FftPlan<kBigN2>::E;
+  constexpr int G = 256 / T;
+  extern __shared__ float2 lds_all[];
+  const DevJob& J = *job;
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  // row = ((s nf + fl) n_inputs + in) 16 + k1
+  const long n_rows = (long)J.n_stations * nf * J.n_inputs * 16;
+  const long row = (long)blockIdx.x * G + g;
+  const bool live = row < n_rows;
+  const long rr = live ? row : 0;
+  const int k1 = (int)(rr % 16);
+  const int in = (int)((rr / 16) % J.n_inputs);
+  const long sf = rr / (16L * J.n_inputs);
+  const int fl = (int)(sf % nf), s = (int)(sf / nf);
+  const float2* x = Z + rr * kBigN2;
+  float2 v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = x[t + e * T];
+  fft_forward<kBigN2>(v, lds_all + g * lds_words<kBigN2>(), TwGlobal{tw}, t);
+  if (!live) return;
+  const DelayRec r = drec[(size_t)s * nf + fl];
+  const bool valid = r.valid != 0;
+  const float dd = (float)r.d;
+  const int P = J.n_pols, M = J.M, n_chan = J.n_chan;
+  const int sb = in / P, p = in - sb * P;
+  const size_t orow = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+  const int8_t* ex = OUT == kOutF32 ? nullptr
+                                    : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
+  // v[r] = X[k1 + 16 k2] with k2 = t + r T; the kept half is k2 < 1024 (r < 8)
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int k = k1 + 16 * (t + q * T);
+    const float2 fd = phasor_turns((float)k * dd * (1.0f / (float)kBigN));
+    const float2 y = valid ? cmul(v[q], fd) : make_float2(0.f, 0.f);
+    put_spec<OUT>(spec, orow + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+  }
+}
+
+size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf) {
+  return N == kBigN ? (size_t)n_stations * nf * n_inputs * kBigN * sizeof(float2) : 0;
+}
+
+static hipError_t launch_big(const DevJob* job, int n_stations, int n_inputs,
+                             const DelayRec* drec, const PhaseRec* prec, const float2* tw,
+                             void* spec, const int8_t* scale_exp, int nf, int out, float2* Z,
+                             hipStream_t s) {
+  if (!Z) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fbig_a, dim3(kBigN2 / kBigChunk, nf, n_stations), dim3(kBigChunk), 0, s,
+                     job, drec, prec, tw, Z, nf);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  constexpr int G = 256 / FftPlan<kBigN2>::T;
+  const size_t lds = (size_t)G * lds_words<kBigN2>() * sizeof(float2);
+  const long rows = (long)n_stations * nf * n_inputs * 16;
+  const dim3 grid((unsigned)((rows + G - 1) / G));
+  if (out == kOutF16)
+    hipLaunchKernelGGL(k_fbig_b<kOutF16>, grid, dim3(256), lds, s, job, drec, tw, Z, spec,
+                       scale_exp, nf);
+  else if (out == kOutF8)
+    hipLaunchKernelGGL(k_fbig_b<kOutF8>, grid, dim3(256), lds, s, job, drec, tw, Z, spec,
+                       scale_exp, nf);
+  else
+    hipLaunchKernelGGL(k_fbig_b<kOutF32>, grid, dim3(256), lds, s, job, drec, tw, Z, spec,
+                       scale_exp, nf);
+  return hipGetLastError();
+}
+
 bool fstage_supported(int N) {
   switch (N) {
-    case 256: case 512: case 1024: case 2048: case 4096: case 8192: case 16384: return true;
+    case 256: case 512: case 1024: case 2048: case 4096: case 8192: case 16384: case 32768:
+      return true;
     default: return false;
   }
 }
 
-hipError_t launch_fstage(int N, const DevJob* job, int n_stations, const DelayRec* drec,
-                         const PhaseRec* prec, const float2* tw, void* spec,
-                         const int8_t* scale_exp, int nf, int waves, int out, unsigned* ctr,
-                         hipStream_t s) {
+hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,
+                         const DelayRec* drec, const PhaseRec* prec, const float2* tw,
+                         void* spec, const int8_t* scale_exp, int nf, int waves, int out,
+                         unsigned* ctr, float2* scratch, hipStream_t s) {
+  if (N == kBigN)
+    return launch_big(job, n_stations, n_inputs, drec, prec, tw, spec, scale_exp, nf, out,
+                      scratch, s);
   if (!ctr) return hipErrorInvalidValue;
   switch (N) {
 #define XC_FCASE(NN)                                                                      \

@@ -100,6 +100,7 @@ struct Layout {
   int nbuf = 1;                   // block buffers (2: F of block b+1 beside X of block b)
   size_t drec_bytes = 0, prec_bytes = 0, spec_bytes = 0;   // per block buffer
   size_t ctr_off = 0;             // F-stage task counter inside each delay-record buffer
+  size_t scratch = 0;             // F-stage scratch (N = 32768 four-step FFT)
 };
 
 ShapeKey shape_key(const xc_setup* s);

@@ -150,6 +150,8 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, b
   off += L.nbuf * L.spec_bytes;
   L.sexp = off;
   if (L.out != kOutF32) off += align_up((size_t)nsb * M * s->n_chan);
+  L.scratch = off;
+  off += align_up(fstage_scratch_bytes(2 * s->n_chan, S, nsb * s->n_pols, L.T));
   L.fps = xmac_frames_per_split(L.T, M, s->n_chan, nsb);
   L.n_slots = L.out == kOutF32 ? (L.T + L.fps - 1) / L.fps : 1;
   L.slot_stride = (size_t)nsb * nbl * s->n_chan;
@@ -256,8 +258,9 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
     e = launch_delays(dj, S, nsb, 0, L.n_scale, drec, prec, ctr0, stream);
     if (e == hipSuccess)
       e = timed(c, XC_K_FSTAGE, stream, [&] {
-        return launch_fstage(N, dj, S, drec, prec, c->d_tw, spec, nullptr, L.n_scale, 0, kOutF32,
-                             ctr0, stream);
+        return launch_fstage(N, dj, S, nsb * s->n_pols, drec, prec, c->d_tw, spec, nullptr,
+                             L.n_scale, 0, kOutF32, ctr0,
+                             reinterpret_cast<float2*>(arena + L.scratch), stream);
       });
     if (e == hipSuccess)
       e = launch_scales(static_cast<const float2*>(spec), nsb, L.n_scale, M, s->n_chan,
@@ -286,8 +289,9 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
     });
     if (e != hipSuccess) return hip_fail(c, e, "delays");
     e = timed(c, XC_K_FSTAGE, stream, [&] {
-      return launch_fstage(N, dj, S, drec_p, prec_p, c->d_tw, spec_p, sexp, nf,
-                           tu.fstage_waves_per_simd, L.out, ctr_p, stream);
+      return launch_fstage(N, dj, S, nsb * s->n_pols, drec_p, prec_p, c->d_tw, spec_p, sexp, nf,
+                           tu.fstage_waves_per_simd, L.out, ctr_p,
+                           reinterpret_cast<float2*>(arena + L.scratch), stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
     if (overlap) {
@@ -658,8 +662,9 @@ int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t
   unsigned* ctr = reinterpret_cast<unsigned*>(p.arena + p.L.drec + p.L.ctr_off);
   hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, ctr, stream);
   if (e == hipSuccess)
-    e = launch_fstage(2 * s->n_chan, dj, s->n_stations, drec, prec, c->d_tw, spectra, nullptr, n,
-                      p.tu.fstage_waves_per_simd, kOutF32, ctr, stream);
+    e = launch_fstage(2 * s->n_chan, dj, s->n_stations, s->n_subbands * s->n_pols, drec, prec,
+                      c->d_tw, spectra, nullptr, n, p.tu.fstage_waves_per_simd, kOutF32, ctr,
+                      reinterpret_cast<float2*>(p.arena + p.L.scratch), stream);
   return e == hipSuccess ? XC_OK : hip_fail(c, e, "debug_spectra");
 }
 

@@ -93,7 +93,8 @@ def test_unpack_bit_exact(xc, corr):
             assert np.array_equal(got, want), (C, s, inp, f)
 
 
-@pytest.mark.parametrize("n_chan,C", [(128, 1), (256, 2), (1024, 16), (4096, 4), (8192, 8)])
+@pytest.mark.parametrize("n_chan,C", [(128, 1), (256, 2), (1024, 16), (4096, 4), (8192, 8),
+                                       (16384, 2)])
 def test_spectra_parity(xc, corr, n_chan, C):
     P, nsb = (2, 2) if C >= 4 else (1, 1)
     job = configs.small_job(n_stations=2, n_subbands=nsb, n_pols=P, n_chan=n_chan, C=C,
@@ -123,6 +124,9 @@ VIS_CASES = [
     ("m_not_mult4", dict(n_stations=7, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=20), 8),
     ("splits", dict(n_stations=3, n_subbands=1, n_pols=2, n_chan=128, C=2, n_frames=700), 600),
     ("m32", dict(n_stations=32, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=30), 0),
+    ("n32768", dict(n_stations=3, n_subbands=1, n_pols=2, n_chan=16384, C=2, n_frames=5), 0),
+    ("n32768_blocks", dict(n_stations=2, n_subbands=2, n_pols=1, n_chan=16384, C=4, n_frames=7),
+     3),
 ]
 
 
