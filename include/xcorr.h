@@ -165,13 +165,17 @@ int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
 /* ---------------------------------------------------------------- tuning */
 /* Launch-shape parameters of the context (0 = library default / autotuned).
  * They change speed only: results are identical for every setting except
- * frames_per_block, which changes FP32 summation order (results stay within
+ * frames_per_block, which changes FP32 summation order, and F-stage variant 5,
+ * which rounds the FFT's last-pass twiddles differently (results stay within
  * the FP32 path's tolerance). */
 typedef struct {
   int32_t fstage_waves_per_simd;   /* F-stage variant: 0 or 1 = default; 2 = the pols of a
                                       subband share their fringe phasors (fewer operations,
                                       more registers); 3 or 4 = at least that many waves per
-                                      SIMD requested (fewer registers) */
+                                      SIMD requested (fewer registers); 5 = split twiddle
+                                      tables (the last FFT pass multiplies two table
+                                      entries: less LDS per workgroup, so more resident
+                                      workgroups, for one complex multiply per twiddle) */
   int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
                                       stages filled by direct memory-to-LDS loads (64-channel
                                       tiles, at most 32 inputs per subband; the default where

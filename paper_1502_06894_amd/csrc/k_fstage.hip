@@ -9,21 +9,39 @@
 
 namespace xc {
 
+// Twiddle tables of the F stage's FFT in LDS: the full per-pass tables
+// (TwLds) or the split ones (TwSplit).
+constexpr int kTwFull = 1, kTwSplit = 2;
+
 template <int N>
+constexpr int tw_default() {
+  // The twiddles are staged in LDS (their tables then cost no registers).  The
+  // split tables win where the full ones cost resident workgroups: N = 4096
+  // (2 instead of 3 per CU) and N = 16384 (the full tables would not fit
+  // beside the exchange buffer); measured on MI355X, the F stage takes 16 %
+  // and 66 % less time there, and 4 % more at N = 2048 and 8192.
+  return N == 4096 || N == 16384 ? kTwSplit : kTwFull;
+}
+
+template <int N, int TWM = tw_default<N>()>
 struct FGeom {
   static constexpr int T = FftPlan<N>::T;
   static constexpr int E = FftPlan<N>::E;
   static constexpr int G = T >= 256 ? 1 : 256 / T;   // frames per workgroup
   static constexpr int WG = T * G;
-  // Up to N = 8192 the twiddles are staged in LDS (their tables then cost no
-  // registers); N = 16384 reads them from memory for every input.
-  static constexpr bool tw_in_lds = N <= 8192;
+  static constexpr int tw_mode = TWM;
+  static constexpr int tw_entries = TWM == kTwFull ? tw_lds_entries<N>() : tw_split_entries<N>();
   // G FFT exchange buffers, the 8-entry level table, the twiddle tables
   static constexpr size_t lut_off = (size_t)G * lds_words<N>() * sizeof(float2);
   static constexpr size_t tw_off = lut_off + 8 * sizeof(float);
-  static constexpr size_t lds_bytes =
-      tw_off + (tw_in_lds ? (size_t)tw_lds_entries<N>() * sizeof(float2) : 0);
+  static constexpr size_t lds_bytes = tw_off + (size_t)tw_entries * sizeof(float2);
 };
+
+// Twiddle source of k_fstage<N, W, ...>: W = 5 selects the split tables.
+template <int N, int W>
+constexpr int fstage_twm() {
+  return W == 5 && N >= 512 ? kTwSplit : tw_default<N>();
+}
 
 // Spectrum element written by the F stage: FP32 complex, or for the MFMA X
 // path the power-of-two-scaled value as FP16 (Re, Im) or OCP e4m3 (Re, Im).
@@ -74,17 +92,20 @@ __device__ inline void load_window(const DevJob& J, int s, const DelayRec& r, in
 // are loaded while the current one is transformed, and the level table and
 // twiddles are set up once per workgroup.
 // W = 0: default; W = 2: the pols of a subband share their fringe phasors;
-// W = 3, 4: ask the compiler for W waves per SIMD (caps registers at 512 / W).
+// W = 3, 4: ask the compiler for W waves per SIMD (caps registers at 512 / W);
+// W = 5: split twiddle tables (TwSplit) at every N >= 512 (the default at
+// N = 4096 and 16384).
 // OUT: spectrum element type (kOutF32, kOutF16, kOutF8); for the low-precision
 // outputs `scale_exp` [n_sb][M][n_chan] holds the power-of-two exponents.
 template <int N, int W, int OUT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
-                               amdgpu_waves_per_eu(W > 2 ? W : 1)))
+                               amdgpu_waves_per_eu(W == 3 || W == 4 ? W : 1)))
     k_fstage(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
              void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf,
              unsigned* __restrict__ ctr) {
-  constexpr int T = FGeom<N>::T, E = FGeom<N>::E, G = FGeom<N>::G;
+  using Gm = FGeom<N, fstage_twm<N, W>()>;
+  constexpr int T = Gm::T, E = Gm::E, G = Gm::G;
   __shared__ int next_task;
   // last-pass butterflies per thread: the thread's bins are t + b T + r N/16
   // (b < BL, r < 16), the kept half r < 8
@@ -104,13 +125,16 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // 2-bit code -> level (offset binary: -3.3359, -1, +1, +3.3359), and four
   // zeros that an invalid frame's lookups are pointed at
   unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds_all);
-  float* lut = reinterpret_cast<float*>(lds_b + FGeom<N>::lut_off);
+  float* lut = reinterpret_cast<float*>(lds_b + Gm::lut_off);
   if (threadIdx.x < 8) {
     const float lv[4] = {-3.3359f, -1.0f, 1.0f, 3.3359f};
     lut[threadIdx.x] = threadIdx.x < 4 ? lv[threadIdx.x] : 0.0f;
   }
-  float2* tw_tab = reinterpret_cast<float2*>(lds_b + FGeom<N>::tw_off);
-  if constexpr (FGeom<N>::tw_in_lds) tw_lds_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
+  float2* tw_tab = reinterpret_cast<float2*>(lds_b + Gm::tw_off);
+  if constexpr (Gm::tw_mode == kTwFull)
+    tw_lds_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
+  else
+    tw_split_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
   __syncthreads();
 
   // With whole waves per frame (T >= 64) the frame index is wave-uniform: the
@@ -207,14 +231,10 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
         const float q = lut_t[(wv[e] >> sh) & 3u];
         v[e] = make_float2(q * zs[e].x, q * zs[e].y);
       }
-      if constexpr (FGeom<N>::tw_in_lds) {
+      if constexpr (Gm::tw_mode == kTwFull) {
         fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
       } else {
-        // an opaque zero keeps the twiddle loads inside the loop (held across
-        // inputs they would not fit in registers)
-        int zero;
-        __asm__ volatile("s_mov_b32 %0, 0" : "=s"(zero));
-        fft_forward<N>(v, lds, TwGlobal{tw + zero}, t);
+        fft_forward<N>(v, lds, TwSplit<N>{tw_tab}, t);
       }
       if (in_blk) {
         const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
@@ -249,7 +269,7 @@ template <int N, int W, int OUT>
 static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* drec,
                             const PhaseRec* prec, const float2* tw, void* spec,
                             const int8_t* scale_exp, int nf, unsigned* ctr, hipStream_t s) {
-  using Gm = FGeom<N>;
+  using Gm = FGeom<N, fstage_twm<N, W>()>;
   // per device: LDS attribute set, and how many workgroups fill the GPU
   static int resident[64] = {};
   int dev = 0;
@@ -280,9 +300,15 @@ static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* dr
                            const int8_t* scale_exp, int nf, int waves, int out, unsigned* ctr,
                            hipStream_t s) {
   if (out == kOutF16)
-    return launch_nw<N, 0, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
+    return waves == 5 ? launch_nw<N, 5, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp,
+                                                 nf, ctr, s)
+                      : launch_nw<N, 0, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp,
+                                                 nf, ctr, s);
   if (out == kOutF8)
-    return launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
+    return waves == 5 ? launch_nw<N, 5, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp,
+                                                nf, ctr, s)
+                      : launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp,
+                                                nf, ctr, s);
   switch (waves) {
     case 2:
       return launch_nw<N, 2, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
@@ -290,6 +316,8 @@ static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* dr
       return launch_nw<N, 3, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     case 4:
       return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
+    case 5:
+      return launch_nw<N, 5, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     default:
       return launch_nw<N, 0, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
   }
@@ -357,6 +385,8 @@ __global__ void __launch_bounds__(kBigChunk)
   }
 }
 
+constexpr int kBigRowIters = 8;   // row groups per k_fbig_b workgroup
+
 template <int OUT>
 __global__ void __launch_bounds__(256)
     k_fbig_b(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
@@ -365,38 +395,45 @@ __global__ void __launch_bounds__(256)
   constexpr int T = FftPlan<kBigN2>::T, E = FftPlan<kBigN2>::E;
   constexpr int G = 256 / T;
   extern __shared__ float2 lds_all[];
+  // G exchange buffers, then the twiddle tables (filled once, used for
+  // kBigRowIters groups of G rows)
+  float2* tw_tab = lds_all + G * lds_words<kBigN2>();
+  tw_lds_fill<kBigN2>(tw_tab, tw, threadIdx.x, blockDim.x);
   const DevJob& J = *job;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
+  const int P = J.n_pols, M = J.M, n_chan = J.n_chan;
   // row = ((s nf + fl) n_inputs + in) 16 + k1
   const long n_rows = (long)J.n_stations * nf * J.n_inputs * 16;
-  const long row = (long)blockIdx.x * G + g;
-  const bool live = row < n_rows;
-  const long rr = live ? row : 0;
-  const int k1 = (int)(rr % 16);
-  const int in = (int)((rr / 16) % J.n_inputs);
-  const long sf = rr / (16L * J.n_inputs);
-  const int fl = (int)(sf % nf), s = (int)(sf / nf);
-  const float2* x = Z + rr * kBigN2;
-  float2 v[E];
+  for (int it = 0; it < kBigRowIters; ++it) {
+    __syncthreads();   // tables written / the previous group's exchange done
+    const long row = ((long)blockIdx.x * kBigRowIters + it) * G + g;
+    const bool live = row < n_rows;
+    const long rr = live ? row : 0;
+    const int k1 = (int)(rr % 16);
+    const int in = (int)((rr / 16) % J.n_inputs);
+    const long sf = rr / (16L * J.n_inputs);
+    const int fl = (int)(sf % nf), s = (int)(sf / nf);
+    const float2* x = Z + rr * kBigN2;
+    float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = x[t + e * T];
-  fft_forward<kBigN2>(v, lds_all + g * lds_words<kBigN2>(), TwGlobal{tw}, t);
-  if (!live) return;
-  const DelayRec r = drec[(size_t)s * nf + fl];
-  const bool valid = r.valid != 0;
-  const float dd = (float)r.d;
-  const int P = J.n_pols, M = J.M, n_chan = J.n_chan;
-  const int sb = in / P, p = in - sb * P;
-  const size_t orow = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
-  const int8_t* ex = OUT == kOutF32 ? nullptr
-                                    : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
-  // v[r] = X[k1 + 16 k2] with k2 = t + r T; the kept half is k2 < 1024 (r < 8)
+    for (int e = 0; e < E; ++e) v[e] = x[t + e * T];
+    fft_forward<kBigN2>(v, lds_all + g * lds_words<kBigN2>(), TwLds<kBigN2>{tw_tab}, t);
+    if (!live) continue;
+    const DelayRec r = drec[(size_t)s * nf + fl];
+    const bool valid = r.valid != 0;
+    const float dd = (float)r.d;
+    const int sb = in / P, p = in - sb * P;
+    const size_t orow = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+    const int8_t* ex = OUT == kOutF32 ? nullptr
+                                      : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
+    // v[r] = X[k1 + 16 k2] with k2 = t + r T; the kept half is k2 < 1024 (r < 8)
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int k = k1 + 16 * (t + q * T);
-    const float2 fd = phasor_turns((float)k * dd * (1.0f / (float)kBigN));
-    const float2 y = valid ? cmul(v[q], fd) : make_float2(0.f, 0.f);
-    put_spec<OUT>(spec, orow + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+    for (int q = 0; q < 8; ++q) {
+      const int k = k1 + 16 * (t + q * T);
+      const float2 fd = phasor_turns((float)k * dd * (1.0f / (float)kBigN));
+      const float2 y = valid ? cmul(v[q], fd) : make_float2(0.f, 0.f);
+      put_spec<OUT>(spec, orow + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+    }
   }
 }
 
@@ -414,9 +451,11 @@ static hipError_t launch_big(const DevJob* job, int n_stations, int n_inputs,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   constexpr int G = 256 / FftPlan<kBigN2>::T;
-  const size_t lds = (size_t)G * lds_words<kBigN2>() * sizeof(float2);
+  const size_t lds =
+      ((size_t)G * lds_words<kBigN2>() + (size_t)tw_lds_entries<kBigN2>()) * sizeof(float2);
   const long rows = (long)n_stations * nf * n_inputs * 16;
-  const dim3 grid((unsigned)((rows + G - 1) / G));
+  const long per_wg = (long)G * kBigRowIters;
+  const dim3 grid((unsigned)((rows + per_wg - 1) / per_wg));
   if (out == kOutF16)
     hipLaunchKernelGGL(k_fbig_b<kOutF16>, grid, dim3(256), lds, s, job, drec, tw, Z, spec,
                        scale_exp, nf);

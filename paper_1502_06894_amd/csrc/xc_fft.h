@@ -149,6 +149,56 @@ __device__ inline void tw_lds_fill(float2* tab, const float2* __restrict__ tw, i
   }
 }
 
+// TwSplit keeps the TwLds tables of every pass but the last, plus a 15 x 16
+// table exp(-2 pi i kl r / N) (entry (r - 1) 16 + kl) after them.  The last
+// pass (Ns = N / 16) forms its twiddle for k = 16 kh + kl as a product:
+// exp(-2 pi i k r / N) = exp(-2 pi i kh r / Ns) exp(-2 pi i kl r / N), the
+// first factor being the previous pass's entry (r - 1) Ns/16 + kh.  The
+// tables shrink from N - R0 to N/16 - R0 + 240 entries for one complex
+// multiply per last-pass twiddle.  Needs N >= 512 (a radix-16 pass with
+// Ns > 1 before the last).
+template <int N>
+struct TwSplit {
+  const float2* tab;
+  template <int R, int Ns>
+  __device__ float2 get(int k, int r) const {
+    constexpr int R0 = first_radix<N>();
+    if constexpr (Ns < N / 16) {
+      return tab[(Ns - R0) + (r - 1) * Ns + k];
+    } else {
+      constexpr int Np = Ns / 16;
+      static_assert(Np >= R0, "TwSplit needs a twiddled pass before the last");
+      const float2 a = tab[(Np - R0) + (r - 1) * Np + (k >> 4)];
+      const float2 b = tab[(N / 16 - R0) + (r - 1) * 16 + (k & 15)];
+      return cmul(a, b);
+    }
+  }
+};
+
+template <int N>
+constexpr int tw_split_entries() {
+  return N / 16 - first_radix<N>() + 15 * 16;
+}
+
+template <int N>
+__device__ inline void tw_split_fill(float2* tab, const float2* __restrict__ tw, int tid, int nthr) {
+  constexpr int R0 = first_radix<N>();
+  constexpr int base = N / 16 - R0;
+  for (int e = tid; e < tw_split_entries<N>(); e += nthr) {
+    if (e < base) {
+      int Ns = R0;
+      while (e >= 16 * Ns - R0) Ns *= 16;
+      const int e2 = e - (Ns - R0);
+      const int r = e2 / Ns + 1, k = e2 - (r - 1) * Ns;
+      tab[e] = tw[k * r * (kTwiddleN / (Ns * 16))];
+    } else {
+      const int e2 = e - base;
+      const int r = e2 / 16 + 1, kl = e2 % 16;
+      tab[e] = tw[kl * r * (kTwiddleN / N)];
+    }
+  }
+}
+
 // One Stockham pass of radix R with sub-transform length Ns over a frame of N
 // points.  On entry v[b + r B] (B = E/R) is input r of butterfly j = t + b T;
 // the outputs are written to lds; the caller synchronises.

@@ -382,7 +382,12 @@ class Correlator:
             raise XcError(XC_E_INVAL, "vis must be a contiguous 4-d complex64 device tensor")
         angles = angles.to(device=vis.device, dtype=torch.float64).contiguous()
         T, nsb, nbl, nch = vis.shape
+        if angles.dim() != 2 or angles.shape[0] != T:
+            raise XcError(XC_E_INVAL, "angles must be [T, S] with T = vis.shape[0]")
         S = angles.shape[1]
+        if nbl != S * (2 * S + 1):
+            raise XcError(XC_E_INVAL, f"vis has {nbl} products; {S} dual-pol stations give "
+                                      f"{S * (2 * S + 1)}")
         fs = XcFeedSetup(T, nsb, S, nch, int(feed))
         self._check(self.lib.xc_feed_correct(self.ctx, C.byref(fs), vis.data_ptr(),
                                              angles.data_ptr(), _stream_ptr(stream)))

@@ -111,6 +111,30 @@ def test_spectra_parity(xc, corr, n_chan, C):
         assert rel_l2(got, Y) < 3e-6, (s, sb, p)
 
 
+@pytest.mark.parametrize("n_chan,C", [(256, 2), (1024, 16), (4096, 4), (8192, 8)])
+def test_split_twiddles_parity(xc, corr, n_chan, C):
+    """F-stage variant 5 (last-pass twiddles as products of two table entries):
+    spectra within the F stage's bound of the oracle, visibilities within TOL."""
+    P, nsb = (2, 2) if C >= 4 else (1, 1)
+    job = configs.small_job(n_stations=3, n_subbands=nsb, n_pols=P, n_chan=n_chan, C=C,
+                            n_frames=9, seed=n_chan + 7)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    try:
+        corr.set_tuning(fstage_waves_per_simd=5)
+        spec = corr.debug_spectra(job, 0, 9).cpu().numpy()
+        vis, w = corr.correlate(job)
+        vis = vis.cpu().numpy()
+    finally:
+        corr.set_tuning(fstage_waves_per_simd=0)
+    for s in range(3):
+        for sb in range(nsb):
+            for p in range(P):
+                Y = fx.station_spectra(job, s, sb, p, np.arange(9))[0]
+                assert rel_l2(spec[sb, :, s * P + p, :], Y) < 3e-6, (s, sb, p)
+    assert rel_l2(vis, V) < TOL
+
+
 VIS_CASES = [
     # name, small_job kwargs, frames_per_block
     ("c1like", dict(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=300), 0),
