@@ -1,8 +1,8 @@
 // Delay-rate fringe search over stacked sub-integrations (the search behind
 // the paper's first-fringe result, section 2): a zero-padded FFT over the
 // channels of every (sub-integration, subband, baseline) row, then per
-// (subband, baseline) a direct transform over sub-integrations, the windowed
-// peak and its parabolic refinement.
+// (subband, baseline) a zero-padded FFT over sub-integrations of every delay
+// column, the windowed peak and its parabolic refinement.
 #include <math.h>
 
 #include "xc_fft.h"
@@ -12,55 +12,91 @@
 namespace xc {
 
 // Delay transform: rows q = (t, sb, bl) of vis [T][n_sb][nbl][n_chan], each
-// zero-padded to D, into F [n_sb][nbl][T][D].  G rows per workgroup, T/16...
-// threads per row as in the F stage's FFT.
+// zero-padded to D, into F [n_sb][nbl][T][D].  A workgroup runs kDelayIters
+// groups of G rows (T threads a row, as in the F stage's FFT), with the
+// twiddles in LDS tables filled once: the full per-pass tables up to D = 2048,
+// the split ones above (less LDS, more resident workgroups).
+constexpr int kDelayIters = 4;
+
 template <int D>
 struct RowGeom {
   static constexpr int T = FftPlan<D>::T;
   static constexpr int E = FftPlan<D>::E;
   static constexpr int G = T >= 256 ? 1 : 256 / T;
   static constexpr int WG = T * G;
-  static constexpr size_t lds_bytes = (size_t)G * lds_words<D>() * sizeof(float2);
+  static constexpr bool split = D >= 4096;
+  static constexpr int tw_entries = split ? tw_split_entries<D>() : tw_lds_entries<D>();
+  static constexpr size_t lds_bytes =
+      ((size_t)G * lds_words<D>() + (size_t)tw_entries) * sizeof(float2);
 };
 
 template <int D>
 __global__ void __launch_bounds__(RowGeom<D>::WG)
     k_fringe_delay(const float2* __restrict__ vis, float2* __restrict__ F,
                    const float2* __restrict__ tw, int n_sub, int n_sb, int nbl, int n_chan) {
-  constexpr int T = RowGeom<D>::T, E = RowGeom<D>::E, G = RowGeom<D>::G;
+  using Gm = RowGeom<D>;
+  constexpr int T = Gm::T, E = Gm::E, G = Gm::G;
   extern __shared__ float2 lds_all[];
+  float2* tab = lds_all + G * lds_words<D>();
+  if constexpr (Gm::split)
+    tw_split_fill<D>(tab, tw, threadIdx.x, blockDim.x);
+  else
+    tw_lds_fill<D>(tab, tw, threadIdx.x, blockDim.x);
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const long n_rows = (long)n_sub * n_sb * nbl;
-  const long q = (long)blockIdx.x * G + g;
-  // the row's indices (rows past the end transform zeros and store nothing)
-  const bool live = q < n_rows;
-  const long qq = live ? q : 0;
-  const int bl = (int)(qq % nbl);
-  const int sb = (int)((qq / nbl) % n_sb);
-  const int ts = (int)(qq / ((long)nbl * n_sb));
-  const float2* x = vis + qq * n_chan;
-  float2 v[E];
+#pragma unroll 1
+  for (int it = 0; it < kDelayIters; ++it) {
+    __syncthreads();   // tables written / the previous group's exchange done
+    const long q = ((long)blockIdx.x * kDelayIters + it) * G + g;
+    // the row's indices (rows past the end transform zeros and store nothing)
+    const bool live = q < n_rows;
+    const long qq = live ? q : 0;
+    const int bl = (int)(qq % nbl);
+    const int sb = (int)((qq / nbl) % n_sb);
+    const int ts = (int)(qq / ((long)nbl * n_sb));
+    const float2* x = vis + qq * n_chan;
+    float2 v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int n = t + e * T;
-    v[e] = live && n < n_chan ? x[n] : make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) {
+      const int n = t + e * T;
+      v[e] = live && n < n_chan ? x[n] : make_float2(0.f, 0.f);
+    }
+    if constexpr (Gm::split)
+      fft_forward<D>(v, lds_all + g * lds_words<D>(), TwSplit<D>{tab}, t);
+    else
+      fft_forward<D>(v, lds_all + g * lds_words<D>(), TwLds<D>{tab}, t);
+    if (!live) continue;
+    float2* out = F + (((size_t)sb * nbl + bl) * n_sub + ts) * D;
+    constexpr int B = E / 16;
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) out[t + b * T + r * (D / 16)] = v[b + r * B];
   }
-  fft_forward<D>(v, lds_all + g * lds_words<D>(), TwGlobal{tw}, t);
-  if (!live) return;
-  float2* out = F + (((size_t)sb * nbl + bl) * n_sub + ts) * D;
-  constexpr int B = E / 16;
-#pragma unroll
-  for (int b = 0; b < B; ++b)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) out[t + b * T + r * (D / 16)] = v[b + r * B];
 }
 
-// Rate transform, peak and refinement: one workgroup per (subband, baseline)
-// map.  Column tiles of kFringeCols delay bins x all T sub-integrations pass
-// through LDS; thread (column c, rate group g) forms G[r, d] for r = g, g + 4,
-// ... with the twiddles exp(-2 pi i m / R) from an LDS table.
-constexpr int kFringeCols = 64;
+// Rate transform, peak and refinement: one workgroup (256 threads) per
+// (subband, baseline) map.  Each round takes GC delay columns; a column's
+// R-point transform over sub-integrations (zero-padded from n_sub) runs on
+// TR = R/16 threads of 16 values (the LDS Stockham FFT) for R >= 32, or in one
+// thread's registers for R <= 16.  Thread (tl, c) = threadIdx tl GC + c, so a
+// wave's loads of one sub-integration row are consecutive columns.
 constexpr int kFringeThreads = 256;
+
+template <int R>
+struct RateGeom {
+  static constexpr bool fft = R >= 32;
+  static constexpr int TR = fft ? R / 16 : 1;       // threads per column
+  static constexpr int E = fft ? 16 : R;            // values per thread
+  static constexpr int GC = kFringeThreads / TR;    // columns per round
+  static constexpr size_t lds_bytes =
+      fft ? ((size_t)GC * lds_words<R>() + (size_t)tw_lds_entries<R>()) * sizeof(float2) : 0;
+};
+
+template <int R>
+__device__ inline void small_dft(float2 (&v)[R]) {
+  if constexpr (R > 1) Dft<R>::run(v);
+}
 
 // signed bin: [-n/2, n/2) for even n; a one-point axis has the single bin 0
 __device__ inline int signed_bin(int b, int n) { return b >= (n + 1) / 2 ? b - n : b; }
@@ -70,14 +106,15 @@ __device__ inline bool better(float a, int ia, float b, int ib) {
   return a > b || (a == b && ia < ib);
 }
 
-__device__ inline float2 rate_point(const float2* __restrict__ Fm, const float2* twr, int n_sub,
-                                    int R, int D, int r, int d) {
-  // G[r, d] from memory (refinement neighbours)
+// G[r, d] by direct summation over sub-integrations (the refinement's
+// neighbours), twiddles exp(-2 pi i m / R) from the global table
+__device__ inline float2 rate_point(const float2* __restrict__ Fm, const float2* __restrict__ tw,
+                                    int n_sub, int R, int D, int r, int d) {
   float2 acc = make_float2(0.f, 0.f);
   int m = 0;
   for (int ts = 0; ts < n_sub; ++ts) {
     const float2 f = Fm[(size_t)ts * D + d];
-    const float2 w = twr[m];
+    const float2 w = tw[(size_t)m * (kTwiddleN / R)];
     acc.x = fmaf(f.x, w.x, fmaf(-f.y, w.y, acc.x));
     acc.y = fmaf(f.x, w.y, fmaf(f.y, w.x, acc.y));
     m = (m + r) & (R - 1);
@@ -90,47 +127,50 @@ __device__ inline float parabola_off(float am, float a0, float ap) {
   return den == 0.f ? 0.f : (am - ap) / (2.f * den);
 }
 
+template <int R>
 __global__ void __launch_bounds__(kFringeThreads)
     k_fringe_rate(const float2* __restrict__ F, const float2* __restrict__ tw,
-                  xc_fringe_peak* __restrict__ peaks, float2* __restrict__ map, int n_sub,
-                  int R, int D, int n_chan, int delay_win, int rate_win, double dnu,
-                  double t_int) {
+                  xc_fringe_peak* __restrict__ peaks, float2* __restrict__ map, int n_sub, int D,
+                  int n_chan, int delay_win, int rate_win, double dnu, double t_int) {
+  using Rg = RateGeom<R>;
+  constexpr int TR = Rg::TR, E = Rg::E, GC = Rg::GC;
   extern __shared__ float2 sh[];
-  float2* twr = sh;                       // [R]
-  float2* tile = sh + R;                  // [n_sub][kFringeCols]
   __shared__ float best_v[kFringeThreads];
   __shared__ int best_i[kFringeThreads];
   const int map_id = blockIdx.x;
   const float2* Fm = F + (size_t)map_id * n_sub * D;
-  for (int m = threadIdx.x; m < R; m += blockDim.x) twr[m] = tw[(size_t)m * (kTwiddleN / R)];
-  const int c = threadIdx.x % kFringeCols, grp = threadIdx.x / kFringeCols;
-  constexpr int kGroups = kFringeThreads / kFringeCols;
+  float2* tab = sh + GC * (Rg::fft ? lds_words<R>() : 0);
+  if constexpr (Rg::fft) tw_lds_fill<R>(tab, tw, threadIdx.x, blockDim.x);
+  const int c = threadIdx.x % GC, tl = threadIdx.x / GC;
   float bv = -1.f;
   int bi = 0x7fffffff;
-  for (int d0 = 0; d0 < D; d0 += kFringeCols) {
-    __syncthreads();   // twiddles written / previous tile consumed
-    for (int i = threadIdx.x; i < n_sub * kFringeCols; i += blockDim.x) {
-      const int ts = i / kFringeCols, cc = i - ts * kFringeCols;
-      tile[i] = Fm[(size_t)ts * D + d0 + cc];
-    }
-    __syncthreads();
+  // D >= 256 is a multiple of GC (<= 256): every round is full
+#pragma unroll 1
+  for (int d0 = 0; d0 < D; d0 += GC) {
     const int d = d0 + c;
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int ts = tl + e * TR;
+      v[e] = ts < n_sub ? Fm[(size_t)ts * D + d] : make_float2(0.f, 0.f);
+    }
+    if constexpr (Rg::fft) {
+      __syncthreads();   // tables written / the previous round's exchange done
+      fft_forward<R>(v, sh + c * lds_words<R>(), TwLds<R>{tab}, tl);
+    } else {
+      small_dft<R>(v);
+    }
+    // v[j] = G[tl + j R/16, d] (FFT), G[j, d] (registers)
     const int ds = signed_bin(d, D);
     const bool d_in = delay_win <= 0 || (ds <= delay_win && ds >= -delay_win);
-    for (int r = grp; r < R; r += kGroups) {
-      float2 acc = make_float2(0.f, 0.f);
-      int m = 0;
-      for (int ts = 0; ts < n_sub; ++ts) {
-        const float2 f = tile[ts * kFringeCols + c];
-        const float2 w = twr[m];
-        acc.x = fmaf(f.x, w.x, fmaf(-f.y, w.y, acc.x));
-        acc.y = fmaf(f.x, w.y, fmaf(f.y, w.x, acc.y));
-        m = (m + r) & (R - 1);
-      }
-      if (map) map[((size_t)map_id * R + r) * D + d] = acc;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int r = Rg::fft ? tl + j * (R / 16) : j;
+      const float2 g = v[j];
+      if (map) map[((size_t)map_id * R + r) * D + d] = g;
       const int rs = signed_bin(r, R);
       const bool in = d_in && (rate_win <= 0 || (rs <= rate_win && rs >= -rate_win));
-      const float a2 = acc.x * acc.x + acc.y * acc.y;
+      const float a2 = g.x * g.x + g.y * g.y;
       const int idx = r * D + d;
       if (in && better(a2, idx, bv, bi)) {
         bv = a2;
@@ -158,7 +198,7 @@ __global__ void __launch_bounds__(kFringeThreads)
     const int k = threadIdx.x;
     const int rr = k == 3 ? (pr + R - 1) % R : k == 4 ? (pr + 1) % R : pr;
     const int dd = k == 1 ? (pd + D - 1) % D : k == 2 ? (pd + 1) % D : pd;
-    pts[k] = rate_point(Fm, twr, n_sub, R, D, rr, dd);
+    pts[k] = rate_point(Fm, tw, n_sub, R, D, rr, dd);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -180,21 +220,45 @@ __global__ void __launch_bounds__(kFringeThreads)
   }
 }
 
+// One attribute call per kernel and device (LDS above 64 KB).
+template <class K>
+static hipError_t allow_lds(K kernel, size_t bytes, bool (&done)[64]) {
+  if (bytes <= 65536) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (done[dev]) return hipSuccess;
+  e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes);
+  if (e == hipSuccess) done[dev] = true;
+  return e;
+}
+
 template <int D>
 static hipError_t launch_delay_d(const float2* vis, float2* F, const float2* tw, int n_sub,
                                  int n_sb, int nbl, int n_chan, hipStream_t s) {
   using Gm = RowGeom<D>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fringe_delay<D>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)Gm::lds_bytes);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static bool done[64] = {};
+  hipError_t e = allow_lds(k_fringe_delay<D>, Gm::lds_bytes, done);
+  if (e != hipSuccess) return e;
   const long rows = (long)n_sub * n_sb * nbl;
-  hipLaunchKernelGGL(k_fringe_delay<D>, dim3((unsigned)((rows + Gm::G - 1) / Gm::G)),
+  const long per_wg = (long)Gm::G * kDelayIters;
+  hipLaunchKernelGGL(k_fringe_delay<D>, dim3((unsigned)((rows + per_wg - 1) / per_wg)),
                      dim3(Gm::WG), Gm::lds_bytes, s, vis, F, tw, n_sub, n_sb, nbl, n_chan);
+  return hipGetLastError();
+}
+
+template <int R>
+static hipError_t launch_rate_r(const xc_fringe_setup* fs, const float2* F, const float2* tw,
+                                xc_fringe_peak* peaks, float2* map, hipStream_t s) {
+  static bool done[64] = {};
+  hipError_t e = allow_lds(k_fringe_rate<R>, RateGeom<R>::lds_bytes, done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fringe_rate<R>, dim3(fs->n_subbands * fs->n_baselines),
+                     dim3(kFringeThreads), RateGeom<R>::lds_bytes, s, F, tw, peaks, map,
+                     fs->n_subints, fs->delay_len, fs->n_chan, fs->delay_win, fs->rate_win,
+                     fs->chan_width_hz, fs->t_int_s);
   return hipGetLastError();
 }
 
@@ -213,18 +277,14 @@ hipError_t launch_fringe(const xc_fringe_setup* fs, const float2* vis, float2* F
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  const size_t lds = ((size_t)fs->rate_len + (size_t)fs->n_subints * kFringeCols) * sizeof(float2);
-  static bool attr_set = false;
-  if (!attr_set) {
-    e = hipFuncSetAttribute((const void*)k_fringe_rate,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
-    if (e != hipSuccess) return e;
-    attr_set = true;
+  switch (fs->rate_len) {
+#define XC_RCASE(RR) \
+  case RR: return launch_rate_r<RR>(fs, F, tw, peaks, map, s);
+    XC_RCASE(1) XC_RCASE(2) XC_RCASE(4) XC_RCASE(8) XC_RCASE(16) XC_RCASE(32) XC_RCASE(64)
+    XC_RCASE(128) XC_RCASE(256) XC_RCASE(512) XC_RCASE(1024)
+#undef XC_RCASE
+    default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_fringe_rate, dim3(fs->n_subbands * fs->n_baselines), dim3(kFringeThreads),
-                     lds, s, F, tw, peaks, map, fs->n_subints, fs->rate_len, fs->delay_len,
-                     fs->n_chan, fs->delay_win, fs->rate_win, fs->chan_width_hz, fs->t_int_s);
-  return hipGetLastError();
 }
 
 }  // namespace xc

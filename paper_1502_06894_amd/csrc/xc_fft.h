@@ -261,7 +261,11 @@ __device__ inline void stockham_last(float2 (&v)[E], const TW& tw, int t) {
 template <int N>
 struct FftPlan;
 
-// N = 256: T = 16, E = 16: 16 x 16
+// N = 256: T = 16, E = 16: 16 x 16 (32..128: short transforms, e.g. over
+// sub-integrations)
+template <> struct FftPlan<32>    { static constexpr int T = 2,    E = 16; };
+template <> struct FftPlan<64>    { static constexpr int T = 4,    E = 16; };
+template <> struct FftPlan<128>   { static constexpr int T = 8,    E = 16; };
 template <> struct FftPlan<256>   { static constexpr int T = 16,   E = 16; };
 template <> struct FftPlan<512>   { static constexpr int T = 32,   E = 16; };
 template <> struct FftPlan<1024>  { static constexpr int T = 64,   E = 16; };
@@ -270,7 +274,8 @@ template <> struct FftPlan<4096>  { static constexpr int T = 256,  E = 16; };
 template <> struct FftPlan<8192>  { static constexpr int T = 512,  E = 16; };
 template <> struct FftPlan<16384> { static constexpr int T = 1024, E = 16; };
 
-// Full transform, radix sequence: 256 = 16.16, 512 = 2.16.16, 1024 = 4.16.16,
+// Full transform, radix sequence: 32 = 2.16, 64 = 4.16, 128 = 8.16,
+// 256 = 16.16, 512 = 2.16.16, 1024 = 4.16.16,
 // 2048 = 8.16.16, 4096 = 16.16.16, 8192 = 2.16.16.16, 16384 = 4.16.16.16.
 // On entry v[e] = x[t + e T]; on exit v[b + r B_last] = X[t + b T + r N / 16].
 // `lds` holds lds_words<N>() float2; the group's threads synchronise with

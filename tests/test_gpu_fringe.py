@@ -82,6 +82,10 @@ def corr(xc):
     (5, 1, 4, 256, 256, 8),          # no delay padding
     (1, 1, 2, 128, 1024, 1),         # a single sub-integration
     (64, 1, 2, 1024, 2048, 64),      # the C2 channel count, no rate padding
+    (100, 1, 2, 300, 4096, 128),     # rate FFT of a ragged sub-integration count
+    (256, 1, 1, 512, 512, 1024),     # the largest rate transform, 256 sub-integrations
+    (3, 2, 2, 1000, 16384, 4),       # the largest delay transform; a four-point rate axis
+    (2, 1, 3, 64, 8192, 2),          # two sub-integrations
 ])
 def test_fringe_parity(corr, T, n_sb, nbl, n_chan, D, R):
     rng = np.random.default_rng(T * 1000 + D)
