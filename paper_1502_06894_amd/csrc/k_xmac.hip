@@ -79,7 +79,10 @@ __global__ void __launch_bounds__(1024)
       const int q = threadIdx.x + i * nthr;
       if (q < n) {
         const int row = q / KC4, cc = q - row * KC4;
-        pre[i] = src[(size_t)(f0 * M + row) * row4 + cc];
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 x = __builtin_nontemporal_load(
+            reinterpret_cast<const f4*>(src) + (size_t)(f0 * M + row) * row4 + cc);
+        pre[i] = make_float4(x.x, x.y, x.z, x.w);
       }
     }
   };
@@ -275,8 +278,11 @@ constexpr int waitcnt_vm_lds(int n) { return (n & 15) | ((n >> 4) << 14) | (7 <<
     ++j;                                                                             \
   }
 
+// Cache policy 2 = non-temporal: the spectra stream through once (measured on
+// MI355X: 4.5 -> 5.1 TB/s, a plain device copy's rate, together with the F
+// stage's non-temporal stores).
 __device__ __forceinline__ void ring_load(const float4* g, float4* l) {
-  __builtin_amdgcn_global_load_lds((glb_void_t*)g, (lds_void_t*)l, 16, 0, 0);
+  __builtin_amdgcn_global_load_lds((glb_void_t*)g, (lds_void_t*)l, 16, 0, 2);
 }
 
 // This lane's operands of one frame: rows gi*4 + x and gj*4 + x, its channel.
