@@ -217,13 +217,13 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
         // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
         // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
         // rho: its constant change 2 phi2 T^2), restarted exactly every kAnchor samples.
-        // Keeping w fixed between anchors leaves out phi2 T^2 e (e - 1) turns at
-        // the e-th sample after an anchor; where that stays below 1e-8 turns for
-        // the whole frame (ground stations, a spacecraft away from perigee) the
-        // first-order recurrence is used (4 fewer operations per sample).  The
-        // test is per (station, subband, frame), hence uniform across the wave.
-        const bool quad =
-            fabs(ph.phi2) * TD * TD * (double)(kAnchor * (kAnchor - 1)) > 1e-8;
+        // Keeping w fixed leaves out phi2 T^2 e (e - 1) turns at the e-th sample
+        // after an anchor; where that stays below 1e-8 turns across all E of a
+        // thread's samples (ground stations, a spacecraft away from perigee) one
+        // anchor and the first-order recurrence serve them all (4 fewer
+        // operations per sample, one anchor instead of E / kAnchor).  The test
+        // is per (station, subband, frame), hence uniform across the wave.
+        const bool quad = fabs(ph.phi2) * TD * TD * (double)(E * (E - 1)) > 1e-8;
         float2 w = make_float2(1.f, 0.f);
         if (quad) {
           const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
@@ -239,16 +239,10 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
             }
           }
         } else {
+          zs[0] = phasor_turns(frac_f(fma(fma(ph.phi2, nc0, ph.phi1), nc0, ph.phi0)));
+          w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc0 + TD)));
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            if (e % kAnchor == 0) {
-              const double nc = nc0 + (double)e * TD;
-              zs[e] = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
-              w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
-            } else {
-              zs[e] = cmul(zs[e - 1], w);
-            }
-          }
+          for (int e = 1; e < E; ++e) zs[e] = cmul(zs[e - 1], w);
         }
       }
       float2 v[E];
