@@ -45,29 +45,39 @@ constexpr int fstage_twm() {
 
 // Spectrum element written by the F stage: FP32 complex, or for the MFMA X
 // path the power-of-two-scaled value as FP16 (Re, Im) or OCP e4m3 (Re, Im).
-// The stores are non-temporal: a block's spectra (gigabytes) are read back by
-// the X stage only after the whole block is written, so keeping them in the
-// caches would only evict lines that are still useful (measured on MI355X: the
-// X stage that follows runs 9 % faster).
-template <int OUT>
+// NT: non-temporal stores, for a wave that writes whole lines (consecutive
+// channels): a block's spectra (gigabytes) are read back by the X stage only
+// after the whole block is written, so keeping them in the caches would only
+// evict lines that are still useful (measured on MI355X: the X stage that
+// follows runs 9 % faster).  Scattered stores (every 16th channel, the
+// N = 32768 row kernel) stay ordinary so that the cache merges their lines.
+template <typename V>
+__device__ inline void store_spec(V* p, V v, bool nt) {
+  if (nt)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <int OUT, bool NT = true>
 __device__ inline void put_spec(void* spec, size_t idx, float2 y, int e) {
   if constexpr (OUT == kOutF32) {
     typedef float f2 __attribute__((ext_vector_type(2)));
     const f2 v = {y.x, y.y};
-    __builtin_nontemporal_store(v, static_cast<f2*>(spec) + idx);
+    store_spec(static_cast<f2*>(spec) + idx, v, NT);
   } else if constexpr (OUT == kOutF16) {
     const float sx = ldexpf(y.x, e), sy = ldexpf(y.y, e);
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     h2 h;
     h.x = (_Float16)sx;
     h.y = (_Float16)sy;
-    __builtin_nontemporal_store(h, static_cast<h2*>(spec) + idx);
+    store_spec(static_cast<h2*>(spec) + idx, h, NT);
   } else {
     // the conversion maps overflow to NaN: saturate at the e4m3 maximum first
     const float sx = fminf(fmaxf(ldexpf(y.x, e), -448.f), 448.f);
     const float sy = fminf(fmaxf(ldexpf(y.y, e), -448.f), 448.f);
     const int pk = __builtin_amdgcn_cvt_pk_fp8_f32(sx, sy, 0, false);
-    __builtin_nontemporal_store((uint16_t)(pk & 0xffff), static_cast<uint16_t*>(spec) + idx);
+    store_spec(static_cast<uint16_t*>(spec) + idx, (uint16_t)(pk & 0xffff), NT);
   }
 }
 
@@ -452,7 +462,7 @@ __global__ void __launch_bounds__(256)
       const int k = k1 + 16 * (t + q * T);
       const float2 fd = phasor_turns((float)k * dd * (1.0f / (float)kBigN));
       const float2 y = valid ? cmul(v[q], fd) : make_float2(0.f, 0.f);
-      put_spec<OUT>(spec, orow + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+      put_spec<OUT, false>(spec, orow + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
     }
   }
 }
