@@ -123,7 +123,7 @@ def cpu_baseline(job, budget_s: float = 12.0, max_frames: int = 8192):
 
 def short_kernel_name(name: str) -> str:
     """'void xc::k_fstage<2048>(...)' -> 'xc::k_fstage<2048>'; other names cut to 60 chars."""
-    n = name.replace("void ", "", 1)
+    n = name.replace("void ", "", 1).replace("(anonymous namespace)::", "")
     depth = 0
     for i, ch in enumerate(n):
         if ch == "<":

@@ -144,16 +144,14 @@ __global__ void __launch_bounds__(kFringeThreads)
   const int c = threadIdx.x % GC, tl = threadIdx.x / GC;
   float bv = -1.f;
   int bi = 0x7fffffff;
-  // D >= 256 is a multiple of GC (<= 256): every round is full
-#pragma unroll 1
-  for (int d0 = 0; d0 < D; d0 += GC) {
-    const int d = d0 + c;
-    float2 v[E];
+  auto load = [&](float2 (&v)[E], int d) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int ts = tl + e * TR;
       v[e] = ts < n_sub ? Fm[(size_t)ts * D + d] : make_float2(0.f, 0.f);
     }
+  };
+  auto search = [&](float2 (&v)[E], int d) {
     if constexpr (Rg::fft) {
       __syncthreads();   // tables written / the previous round's exchange done
       fft_forward<R>(v, sh + c * lds_words<R>(), TwLds<R>{tab}, tl);
@@ -177,6 +175,18 @@ __global__ void __launch_bounds__(kFringeThreads)
         bi = idx;
       }
     }
+  };
+  // D >= 256 is a multiple of GC (<= 256): every round is full.  Two rounds'
+  // columns are loaded together, so the second's loads overlap the first's
+  // transform.
+#pragma unroll 1
+  for (int d0 = 0; d0 < D; d0 += 2 * GC) {
+    const bool two = d0 + GC < D;
+    float2 v0[E], v1[E];
+    load(v0, d0 + c);
+    if (two) load(v1, d0 + GC + c);
+    search(v0, d0 + c);
+    if (two) search(v1, d0 + GC + c);
   }
   best_v[threadIdx.x] = bv;
   best_i[threadIdx.x] = bi;
