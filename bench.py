@@ -228,21 +228,22 @@ def run_c3(a):
     t_loop = (time.perf_counter() - t0) / a.steps
     log(f"per-job loop: {t_loop * 1e3:.1f} ms per batch, {ss / t_loop / 1e9:.1f} G ss/s")
     refs = [(v.clone(), w.clone()) for v, w in outs]
-    bws = corr.batch_workspace(jobs, n_lanes=a.lanes)
+    lanes = a.lanes or 8
+    bws = corr.batch_workspace(jobs, n_lanes=lanes)
     bouts = [corr.alloc_output(j) for j in jobs]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        corr.correlate_batch(jobs, n_lanes=a.lanes, graph=True, outs=bouts, workspace=bws,
+        corr.correlate_batch(jobs, n_lanes=lanes, graph=True, outs=bouts, workspace=bws,
                              stream=stream)     # capture
         stream.synchronize()
         t0 = time.perf_counter()
         for _ in range(a.steps):
-            corr.correlate_batch(jobs, n_lanes=a.lanes, graph=True, outs=bouts, workspace=bws,
+            corr.correlate_batch(jobs, n_lanes=lanes, graph=True, outs=bouts, workspace=bws,
                                  stream=stream)
         stream.synchronize()
     t_batch = (time.perf_counter() - t0) / a.steps
     same = all(torch.equal(v, rv) and torch.equal(w, rw) for (v, w), (rv, rw) in zip(bouts, refs))
-    log(f"batch ({a.lanes} lanes, graph replay): {t_batch * 1e3:.1f} ms, "
+    log(f"batch ({lanes} lanes, graph replay): {t_batch * 1e3:.1f} ms, "
         f"{ss / t_batch / 1e9:.1f} G ss/s; identical to per-job results: {same}")
     return {
         "metric": "correlated station-samples/s", "value": round(ss / t_batch / 1e9, 2),
@@ -252,7 +253,7 @@ def run_c3(a):
         "config": {"workload": f"C3: {len(jobs)} uneven sub-integration jobs (stations 2-20, "
                                f"subbands 1-16, channels 128-8192, 0.1-4 s) over a 20-station "
                                f"x 16-stream x 4.5 s device-resident pool",
-                   "lanes": a.lanes, "graph": True, "station_samples_per_step": ss},
+                   "lanes": lanes, "graph": True, "station_samples_per_step": ss},
         "per_job_loop": {"value": round(ss / t_loop / 1e9, 2), "ms_per_step": round(t_loop * 1e3, 3)},
         "batch_over_loop": round(t_loop / t_batch, 3),
         "identical_to_per_job": bool(same),
@@ -314,7 +315,8 @@ def run_c5(a):
     ss = sum(j.station_samples for _, j in trace)
     span = trace[-1][0]
     log(f"{len(trace)} requests over {span:.2f} s, offered {ss / span / 1e9:.1f} G ss/s")
-    srv = xcorr.Server(0, hbm_budget_bytes=a.budget_gb << 30, max_slots=a.lanes)
+    slots = a.lanes or 16      # more slots than C3's lanes: small requests need not queue
+    srv = xcorr.Server(0, hbm_budget_bytes=a.budget_gb << 30, max_slots=slots)
     tickets = []
     t0 = time.perf_counter()
     for arr, job in trace:
@@ -336,7 +338,7 @@ def run_c5(a):
         "config": {"workload": f"C5: Poisson trace, {len(trace)} requests at {a.rate:g}/s "
                                f"(stations 3-20, subbands 1-16, channels 256-{2 ** a.max_log2_chan}, "
                                f"0.1-4 s) over the device-resident pool",
-                   "slots": a.lanes, "hbm_budget_gb": a.budget_gb},
+                   "slots": slots, "hbm_budget_gb": a.budget_gb},
         "latency_ms": {"p50": round(st["p50_ms"], 2), "p99": round(st["p99_ms"], 2),
                        "mean": round(st["mean_ms"], 2)},
         "offered_g_per_s": round(ss / span / 1e9, 2),
@@ -502,7 +504,8 @@ def main():
     ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
                     help="c4: precision reported as the value")
     ap.add_argument("--jobs", type=int, default=64, help="c3: number of jobs")
-    ap.add_argument("--lanes", type=int, default=8, help="c3/c5: concurrent lanes")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="c3: concurrent lanes (default 8); c5: server slots (default 16)")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: mean arrival rate (1/s)")
     ap.add_argument("--max-log2-chan", type=int, default=14, help="c5: largest log2(channels)")
