@@ -137,7 +137,11 @@ size_t xc_workspace_bytes(const xc_ctx* ctx, const xc_setup* setup, const xc_sta
 /* Correlate one sub-integration.  st: host [n_stations]; out: host struct of
  * device pointers; workspace: device, ws_bytes >= xc_workspace_bytes().  Async
  * on `stream`; results are complete when the stream reaches this point.
- * V = mean over valid frames (unnormalised FFT); W = 0 gives V = 0. */
+ * V = mean over valid frames (unnormalised FFT); W = 0 gives V = 0.  Frames
+ * whose shifted window leaves a station's recording, or touches a recording
+ * frame that fails its sync check, are not errors: they count 0 in W.  The
+ * call returns before the GPU has judged any frame, so partial coverage is
+ * reported by W (< n_frames), not by the return code. */
 int xc_correlate_subint(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
                         const xc_output* out, void* workspace, size_t ws_bytes, void* stream);
 
