@@ -83,6 +83,18 @@ def traffic_from_profile(kind: str, src_hash: str, launches_units: float):
     return e.get("bytes_per_launch")
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), for the CPU-baseline record."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(job, budget_s: float = 12.0, max_frames: int = 8192):
     """The FP64 oracle on a bounded sample of the same workload (subband 0, all inputs)."""
     import torch
@@ -115,7 +127,7 @@ def cpu_baseline(job, budget_s: float = 12.0, max_frames: int = 8192):
     dt = time.perf_counter() - t0
     ss = job.M * done * job.N
     return {"value": ss / dt / 1e9, "unit": "G station-samples/s", "cores": cores,
-            "kind": "oracle",
+            "cpu": cpu_model(), "kind": "oracle",
             "sample": f"subband 0 of {job.n_subbands}, all {job.M} inputs, frames 0..{done - 1} "
                       f"of {job.n_frames} ({ss:.3e} station-samples in {dt:.1f} s, "
                       f"{cores} threads)"}
@@ -406,7 +418,7 @@ def run_fringe(a):
                     break
             if dtc > 10.0:
                 break
-        cpu = {"value": done / dtc, "unit": "maps/s", "cores": 1,
+        cpu = {"value": done / dtc, "unit": "maps/s", "cores": 1, "cpu": cpu_model(),
                "kind": "oracle",
                "sample": (f"{done} of the {maps} maps, in groups of 30 "
                           f"({dtc:.1f} s, numpy FFTs, one thread)")}
@@ -467,7 +479,7 @@ def run_feed(a):
             if dtc > 10.0:
                 break
         cpu = {"value": done * n_sb * nbl * n_chan / dtc / 1e9, "unit": "G products/s",
-               "cores": 1, "kind": "oracle",
+               "cores": 1, "cpu": cpu_model(), "kind": "oracle",
                "sample": f"{done} of the {T} sub-integrations ({dtc:.1f} s, numpy, one thread)"}
     return {
         "metric": "feed-corrected products/s", "value": round(V.numel() / dt / 1e9, 2),
