@@ -7,11 +7,15 @@
 // so three 32x32 MFMA tiles per channel (G11 = Re Re^T, G22 = Im Im^T,
 // G21 = Im Re^T) accumulate in FP32 with K = frames.  A workgroup owns KC
 // channels of one subband; spectra arrive in the F stage's [frame][input]
-// [channel] order and are transposed into LDS as [channel word][input][frame]
-// so that each lane's MFMA operand (4 FP16 or 8 FP8 consecutive frames of one
-// input) is a single 16-byte LDS read.  After the block, G21 is transposed
-// through LDS, every element is unscaled by 2^-(e_i + e_j) and added to the
-// FP64 accumulator slot of the FP32 path.
+// [channel] order.  FP16 keeps that order in LDS, rows padded to RW + 1 words
+// and frames to 32 (RW + 1) + 1, so that both the row-wise stores
+// (consecutive lanes, consecutive words) and each lane's operand gather (one
+// word per frame, 32 lanes 32 inputs apart) hit distinct banks.  FP8 (half the
+// words per row, twice the frames per operand) transposes into LDS as
+// [channel word][input][frame], so that a lane's 8 frames are two 16-byte
+// reads (measured faster there).  After the block, G21 is transposed through
+// LDS, every element is unscaled by 2^-(e_i + e_j) and added to the FP64
+// accumulator slot of the FP32 path.
 #include "xc_launch.h"
 
 namespace xc {
@@ -63,11 +67,14 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   constexpr int NW = KC / CPW;                       // waves
   constexpr int NT = 64 * NW;
   constexpr int RW = OUT == kOutF16 ? KC : KC / 2;   // 32-bit words per (frame, input) row
-  constexpr int FP = FB + 4;                         // LDS frame stride (padding)
+  constexpr int RS = RW + 1;                         // FP16 LDS row stride (words)
+  constexpr int FS = 32 * RS + 1;                    // FP16 LDS frame stride (words)
+  constexpr int FP = FB + 4;                         // FP8 LDS frame stride (padding)
   constexpr int KSTEP = OUT == kOutF16 ? 8 : 16;     // frames per MFMA
   constexpr int OPF = KSTEP / 2;                     // frames per lane operand
-  extern __shared__ uint32_t lds[];                  // 2 stages of [RW][32][FP] words
-  constexpr int STAGE = RW * 32 * FP;
+  // 2 stages: FP16 [FB][32][RS] (+ padding), FP8 [RW][32][FP]
+  extern __shared__ uint32_t lds[];
+  constexpr int STAGE = OUT == kOutF16 ? FB * FS : RW * 32 * FP;
   const DevJob& J = *job;
   const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
   const int sb = blockIdx.y;
@@ -77,7 +84,7 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   const size_t row_words = OUT == kOutF16 ? (size_t)n_chan : (size_t)n_chan / 2;   // per spectrum row
   const uint32_t* src = spec + (size_t)sb * nf * M * row_words + (size_t)k0 * RW / KC;
 
-  // inputs m >= M (and the padding rows) read zeros
+  // inputs m >= M (and the padding) read zeros
   for (int q = threadIdx.x; q < 2 * STAGE; q += NT) lds[q] = 0u;
 
   float16_t acc11[CPW], acc22[CPW], acc21[CPW];
@@ -89,7 +96,7 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   }
 
   // stage loader: FB frames x M inputs x RW words, read along the channel words
-  // (coalesced) and written transposed as [word][input][frame]
+  // (coalesced) and stored row by row
   constexpr int PER = (FB * 32 * RW + NT - 1) / NT;
   uint32_t pre[PER];
   auto gload = [&](int f0) {
@@ -108,7 +115,12 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
       const int q = threadIdx.x + i * NT;
       const int w = q % RW, r = q / RW;
       const int fb = r / M, mm = r - fb * M;
-      if (r < FB * M) lds[buf * STAGE + (w * 32 + mm) * FP + fb] = pre[i];
+      if (r < FB * M) {
+        if constexpr (OUT == kOutF16)
+          lds[buf * STAGE + fb * FS + mm * RS + w] = pre[i];
+        else
+          lds[buf * STAGE + (w * 32 + mm) * FP + fb] = pre[i];
+      }
     }
   };
 
@@ -128,19 +140,20 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
       for (int ks = 0; ks < FB / KSTEP; ++ks) {
         const int fbase = ks * KSTEP + g * OPF;
         if constexpr (OUT == kOutF16) {
-          const uint4 w = *reinterpret_cast<const uint4*>(st + (ch * 32 + m) * FP + fbase);
-          const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+          // 4 frames of input m, channel word ch
+          const uint32_t* p = st + fbase * FS + m * RS + ch;
           half4_t re, im;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            re[e] = __builtin_bit_cast(_Float16, (uint16_t)(ww[e] & 0xffffu));
-            im[e] = __builtin_bit_cast(_Float16, (uint16_t)(ww[e] >> 16));
+            const uint32_t w = p[e * FS];
+            re[e] = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+            im[e] = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
           }
           acc11[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(re, re, acc11[c], 0, 0, 0);
           acc22[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, im, acc22[c], 0, 0, 0);
           acc21[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, re, acc21[c], 0, 0, 0);
         } else {
-          // 8 frames of this channel: half-word (ch & 1) of word ch / 2
+          // 8 frames of input m, channel ch: half-word (ch & 1) of word ch / 2
           const uint32_t* p = st + ((ch >> 1) * 32 + m) * FP + fbase;
           const uint4 w0 = *reinterpret_cast<const uint4*>(p);
           const uint4 w1 = *reinterpret_cast<const uint4*>(p + 4);
@@ -201,7 +214,8 @@ static hipError_t launch_cfg(const DevJob* job, int n_chan, int n_subbands, cons
                              const int8_t* scale_exp, double2* vacc, int nf, hipStream_t s) {
   constexpr int NW = KC / CPW;
   constexpr int RW = OUT == kOutF16 ? KC : KC / 2;
-  size_t lds = 2 * (size_t)RW * 32 * (FB + 4) * sizeof(uint32_t);
+  size_t lds = 2 * (OUT == kOutF16 ? (size_t)FB * (32 * (RW + 1) + 1)
+                                    : (size_t)RW * 32 * (FB + 4)) * sizeof(uint32_t);
   const size_t scr = (size_t)NW * 32 * 33 * sizeof(float);
   if (scr > lds) lds = scr;
   static bool attr_set = false;
