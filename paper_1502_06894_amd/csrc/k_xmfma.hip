@@ -77,8 +77,15 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   constexpr int STAGE = OUT == kOutF16 ? FB * FS : RW * 32 * FP;
   const DevJob& J = *job;
   const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
-  const int sb = blockIdx.y;
-  const int k0 = blockIdx.x * KC;
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
+  // workgroup b takes tile (b mod 8) (tiles / 8) + b / 8; each XCD then works
+  // through a contiguous run of channel tiles, and tiles that share cache lines
+  // (FP16 rows of 64 B, FP8 rows of 32 B in 128-byte lines) share one L2.
+  const int n_tiles = gridDim.x * gridDim.y;
+  const int b = blockIdx.x + gridDim.x * blockIdx.y;
+  const int tile = n_tiles % 8 == 0 ? (b % 8) * (n_tiles / 8) + b / 8 : b;
+  const int sb = tile / gridDim.x;
+  const int k0 = (tile - sb * gridDim.x) * KC;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 31, g = lane >> 5;
   const size_t row_words = OUT == kOutF16 ? (size_t)n_chan : (size_t)n_chan / 2;   // per spectrum row
