@@ -1,4 +1,4 @@
-"""FX correlation, steps O1-O10, in float64 (long double for the fringe phase).
+"""FX correlation, steps O1-O11, in float64 (long double for the fringe phase).
 
 TEST INFRASTRUCTURE ONLY -- see the package docstring.
 
@@ -9,7 +9,9 @@ its delay-model paragraphs (delays for an antenna with arbitrary, changing
 position and velocity, relativistic terms, and the spacecraft-to-tracking
 station transmission delay, all of which arrive here summed into one delay
 polynomial per station).  The paper gives no formulas; each step states the
-convention it fixes.
+convention it fixes.  O11 (optional per station) is the correction of the
+spacecraft's acceleration-era delay drift that the paper lists among its
+future improvements (section 2, the closing list).
 """
 from __future__ import annotations
 
@@ -114,6 +116,34 @@ def frame_valid(words: np.ndarray, C: int, first_sample: int, sub_start: int, N:
     return base, valid
 
 
+def frame_rates(delay_poly, sub_start: int, N: int, fs: float, frames: np.ndarray) -> np.ndarray:
+    """O11 input: the delay rate rho = tau'(t_mid) (s/s, i.e. samples of delay per
+    sample) at each frame's centre, from the derivative polynomial by Horner."""
+    f = np.asarray(frames, dtype=np.int64)
+    num = np.int64(sub_start) + f * np.int64(N) + np.int64(N // 2)
+    t_mid = num.astype(np.float64) / np.float64(fs)
+    c = np.asarray(delay_poly, dtype=np.float64)
+    if c.shape[0] < 2:
+        return np.zeros(f.shape[0])
+    dc = c[1:] * np.arange(1, c.shape[0], dtype=np.float64)
+    return horner(dc, t_mid)
+
+
+def rate_corrected(X: np.ndarray, Xr: np.ndarray, rho: np.ndarray, k: np.ndarray, N: int):
+    """O11: first-order correction of the delay's drift inside a frame.
+
+    Inside frame f the delay is D_c + rho (n - N/2) samples, while the window
+    and the fractional-delay phase take D_c for the whole frame.  The aligned
+    samples are therefore the window resampled about the frame centre,
+    a(n) = w(N/2 + (1 + rho)(n - N/2) + d), whose spectrum to first order in rho
+    is (1 - rho) W(k) + (2 pi i rho k / N) Wr(k), with Wr the spectrum of
+    (n - N/2) w(n).  X, Xr: [nf, K] spectra of w and of the ramp-weighted
+    window; rho: [nf]; k: [K] (signed for a full band).
+    """
+    r = np.asarray(rho, dtype=np.float64)[:, None]
+    return (1.0 - r) * X + (2j * np.pi / N) * r * np.asarray(k, dtype=np.float64)[None, :] * Xr
+
+
 # ----------------------------------------------------------------- per-sample fringe phase
 
 def _horner_ld(coeffs, t: np.ndarray) -> np.ndarray:
@@ -187,10 +217,16 @@ def station_spectra(job, s: int, sb: int, p: int, frames: np.ndarray, *,
     y, d, valid = rotated_samples(job, s, sb, p, frames, rotate=rotate, words=words)
     K = N if full_band else N // 2
     Y = scipy.fft.fft(y, axis=1, workers=_WORKERS)[:, :K]                   # O7
+    k = np.arange(K, dtype=np.float64)
+    if full_band:
+        k = np.where(k < N // 2, k, k - N)
+    st = job.stations[s]
+    if getattr(st, "rate_correct", False):                                 # O11
+        ramp = np.arange(N, dtype=np.float64) - N // 2
+        Yr = scipy.fft.fft(y * ramp[None, :], axis=1, workers=_WORKERS)[:, :K]
+        rho = frame_rates(st.delay_poly, job.sub_start, N, job.fs_hz, frames)
+        Y = rate_corrected(Y, Yr, rho, k, N)
     if frac:                                                               # O8
-        k = np.arange(K, dtype=np.float64)
-        if full_band:
-            k = np.where(k < N // 2, k, k - N)
         Y = Y * np.exp(2j * np.pi * k[None, :] * d[:, None] / N)
     Y[~valid] = 0.0
     return Y, valid

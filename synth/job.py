@@ -21,6 +21,7 @@ class Station:
     phase_poly: Optional[np.ndarray] = None   # float64 [n_subbands, deg+1]: fringe phase in turns
     poly_span: Tuple[float, float] = (0.0, 120.0)
     station_id: int = 0
+    rate_correct: bool = False        # correct the delay's drift inside each frame (O11)
 
     @property
     def n_frames_m5b(self) -> int:

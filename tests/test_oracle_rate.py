@@ -1,0 +1,79 @@
+"""Oracle pins: intra-frame delay-rate correction (oracle/fx.py, O11).
+
+Pinned at the signal level: a band-limited signal whose samples were taken on
+a time axis stretched by (1 + rho) about the frame centre must come back, after
+the correction, to the spectrum of the unstretched samples with an error that
+is second order in rho (a missing or mis-signed term leaves a first-order
+error, which the error-ratio test rejects); with rho = 0 or the flag off the
+spectra are unchanged; the rate is the derivative of the delay polynomial.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import scipy.fft
+
+from oracle import fx
+from synth import configs
+
+
+def _bandlimited(rng, N, n_tones=40, lo=0.05, hi=0.45):
+    """A sum of tones (frequencies in cycles/sample), evaluable at any time."""
+    f = rng.uniform(lo, hi, n_tones)
+    a = rng.normal(size=n_tones) + 1j * rng.normal(size=n_tones)
+    return lambda t: (a[None, :] * np.exp(2j * np.pi * f[None, :] * np.asarray(t)[:, None])).sum(1)
+
+
+def _errors(rho, N=2048, seed=3):
+    rng = np.random.default_rng(seed)
+    sig = _bandlimited(rng, N)
+    n = np.arange(N, dtype=np.float64)
+    c = N // 2
+    ideal = sig(n)                                   # the aligned samples a(n)
+    w = sig(c + (n - c) / (1.0 + rho))               # the window: a(n) = w(c + (1 + rho)(n - c))
+    A = scipy.fft.fft(ideal)[: N // 2]
+    W = scipy.fft.fft(w)[: N // 2]
+    Wr = scipy.fft.fft(w * (n - c))[: N // 2]
+    k = np.arange(N // 2, dtype=np.float64)
+    Y = fx.rate_corrected(W[None], Wr[None], np.array([rho]), k, N)[0]
+    norm = np.linalg.norm(A)
+    return np.linalg.norm(W - A) / norm, np.linalg.norm(Y - A) / norm
+
+
+@pytest.mark.parametrize("rho,N", [(3e-5, 2048), (-3e-5, 2048), (1e-4, 2048), (3e-5, 8192)])
+def test_correction_restores_the_unstretched_spectrum(rho, N):
+    before, after = _errors(rho, N=N)
+    assert before > 0.02 * abs(rho) / 3e-5 * N / 2048   # the drift is visible (~k rho)
+    assert after < 0.12 * before                        # and mostly removed
+
+
+def test_residual_is_second_order():
+    b1, a1 = _errors(1e-4)
+    b2, a2 = _errors(2e-4)
+    assert 1.8 < b2 / b1 < 2.2                       # uncorrected: first order
+    assert 3.5 < a2 / a1 < 4.5                       # corrected: second order
+
+
+def test_zero_rate_and_flag_off_are_identity():
+    job = configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=4)
+    Y0, _ = fx.station_spectra(job, 0, 0, 0, np.arange(4))
+    # constant delay polynomial: rho = 0, the correction is exactly the identity
+    st = dataclasses.replace(job.stations[0], rate_correct=True,
+                             delay_poly=np.array([job.stations[0].delay_poly[0]]))
+    j1 = dataclasses.replace(job, stations=[st] + list(job.stations[1:]))
+    j0 = dataclasses.replace(job, stations=[dataclasses.replace(st, rate_correct=False)]
+                             + list(job.stations[1:]))
+    Ya, _ = fx.station_spectra(j1, 0, 0, 0, np.arange(4))
+    Yb, _ = fx.station_spectra(j0, 0, 0, 0, np.arange(4))
+    assert np.array_equal(Ya, Yb)
+
+
+def test_rate_is_the_polynomial_derivative():
+    poly = [0.4, 1.0e-5, 3e-10, -2e-13, 1e-16, -4e-20]
+    fs, N, sub_start = 32e6, 2048, int(37.0 * 32e6)
+    f = np.array([0, 1000, 60000])
+    rho = fx.frame_rates(poly, sub_start, N, fs, f)
+    t = (sub_start + f * N + N // 2) / fs
+    h = 1e-3
+    num = (np.polyval(poly[::-1], t + h) - np.polyval(poly[::-1], t - h)) / (2 * h)
+    assert np.max(np.abs(rho - num)) < 1e-12
