@@ -77,3 +77,32 @@ def test_rate_is_the_polynomial_derivative():
     h = 1e-3
     num = (np.polyval(poly[::-1], t + h) - np.polyval(poly[::-1], t - h)) / (2 * h)
     assert np.max(np.abs(rho - num)) < 1e-12
+
+
+def test_physics_drift_correction_restores_coherence():
+    """Exact-physics recordings (true per-sample delays) of a spacecraft whose delay
+    drifts 2e-4 s/s: across a 4096-sample frame the drift reaches +-0.41 samples,
+    which decorrelates the upper band (measured: 0.380 against 0.445 in the lower
+    band); the correction restores it (0.440 against 0.447)."""
+    from synth import physics
+    fs, N = 32e6, 4096
+    job = physics.two_station_job(fs=fs, N=N, n_frames=96, sub_start=int(37.0 * fs),
+                                  model_polys=[[0.011, 0.0], [0.08, 2e-4]],
+                                  residual_delay_s=[0.0, 0.0], lo_hz=4.82e9, rho=0.5,
+                                  seed=1502068951)
+    on = dataclasses.replace(job, stations=[job.stations[0],
+                                            dataclasses.replace(job.stations[1],
+                                                                rate_correct=True)])
+    K = N // 2
+    coh = {}
+    for name, j in (("off", job), ("on", on)):
+        V, _ = fx.correlate(j, threads=8)
+        v01 = V[0, fx.baseline_index(0, 1, 2)]
+        a0, a1 = V[0, fx.baseline_index(0, 0, 2)].real, V[0, fx.baseline_index(1, 1, 2)].real
+        c = np.abs(v01) / np.sqrt(a0 * a1)
+        coh[name] = (c[K // 8: K // 4].mean(), c[3 * K // 4: 7 * K // 8].mean())
+    low_off, top_off = coh["off"]
+    low_on, top_on = coh["on"]
+    assert top_off < 0.9 * low_off                   # the drift decorrelates the band top
+    assert top_on > 0.97 * low_on                    # the correction restores it
+    assert abs(low_on - low_off) < 0.03 * low_off    # and leaves the band bottom alone
