@@ -112,6 +112,13 @@ typedef struct {
   const double*  phase_poly;   /* host [n_subbands][poly_deg+1] fringe phase in turns of the
                                   same t, or NULL: phase = lo_hz[sb] * tau(t) */
   double         poly_t0, poly_t1;  /* validity span of the polynomials (seconds) */
+  int32_t        rate_correct; /* 1: correct the delay's drift inside each frame (the delay
+                                  runs D_c + rho (n - N/2) samples across a frame, rho the
+                                  delay rate at its centre): each kept spectrum becomes
+                                  (1 - rho) Y(k) + (2 pi i rho k / N) Yr(k), Yr the spectrum
+                                  of the ramp-weighted window -- first order in rho, for a
+                                  spacecraft whose delay rate smears long frames.  FP32 path
+                                  and n_chan <= 8192 only (XC_E_INVAL otherwise); 0: off */
 } xc_station;
 
 typedef struct {

@@ -130,6 +130,12 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // W = 2: a subband's pols share one set of fringe phasors (both see the same
   // fringe phase), held in registers from the first pol to the second
   constexpr bool kShare = W == 2;
+  // W = kFstageRatePass: the drift-correction pass over the stations that ask
+  // for it: the window is weighted by the ramp (n - N/2) before the transform,
+  // and the stored spectrum Y (from the regular pass) becomes
+  // (1 - rho) Y + (2 pi i rho k / N) fd Yr
+  constexpr bool kRamp = W == kFstageRatePass;
+  static_assert(!kRamp || OUT == kOutF32, "the drift correction rewrites FP32 spectra");
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
@@ -217,7 +223,10 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
 
     // the fringe phasors of a subband, kept for its second pol when kShare
     float2 zs[E];
-    for (int in = 0; in < J.n_inputs; ++in) {
+    // (the drift-correction pass skips the stations that do not ask for it; the
+    // station is the same for the whole workgroup)
+    const int n_in = kRamp && !J.st[s].rate_correct ? 0 : J.n_inputs;
+    for (int in = 0; in < n_in; ++in) {
       const int sb = in / P, p = in - sb * P;
       const int sh = sh0 + 2 * J.stream_map[in];
       if (!kShare || p == 0) {
@@ -258,7 +267,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
       float2 v[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const float q = lut_t[(wv[e] >> sh) & 3u];
+        float q = lut_t[(wv[e] >> sh) & 3u];
+        if constexpr (kRamp) q *= (float)(t + e * T - N / 2);
         v[e] = make_float2(q * zs[e].x, q * zs[e].y);
       }
       if constexpr (Gm::tw_mode == kTwFull) {
@@ -275,8 +285,18 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
 #pragma unroll
           for (int rr = 0; rr < 8; ++rr) {
             const int k = t + b * T + rr * (N / 16);
-            const float2 y = valid ? cmul(v[b + rr * BL], fd[b][rr]) : make_float2(0.f, 0.f);
-            put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+            if constexpr (kRamp) {
+              float2* sp = static_cast<float2*>(spec) + row + k;
+              if (valid) {
+                const float2 old = *sp;
+                const float2 yr = cmul(v[b + rr * BL], fd[b][rr]);
+                const float rho = r.rate, a = 6.28318530717958648f * rho * (float)k / (float)N;
+                *sp = make_float2((1.0f - rho) * old.x - a * yr.y, (1.0f - rho) * old.y + a * yr.x);
+              }
+            } else {
+              const float2 y = valid ? cmul(v[b + rr * BL], fd[b][rr]) : make_float2(0.f, 0.f);
+              put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+            }
           }
       }
       __syncthreads();   // the next input reuses lds
@@ -348,6 +368,11 @@ static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* dr
       return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     case 5:
       return launch_nw<N, 5, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
+    case kFstageRatePass:
+      if constexpr (N <= kMaxRateCorrectN)
+        return launch_nw<N, kFstageRatePass, kOutF32>(job, n_stations, drec, prec, tw, spec,
+                                                      nullptr, nf, ctr, s);
+      return hipErrorInvalidValue;
     default:
       return launch_nw<N, 0, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
   }

@@ -40,7 +40,10 @@ __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
                          unsigned* __restrict__ ctr) {
   const int fl = blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
-  if (ctr && fl == 0 && s == 0) *ctr = 0u;
+  if (ctr && fl == 0 && s == 0) {
+    ctr[0] = 0u;   // the F stage's task counter
+    ctr[1] = 0u;   // the drift-correction pass's
+  }
   if (fl >= nf) return;
   const DevJob& J = *job;
   const DevStation& S = J.st[s];
@@ -55,10 +58,12 @@ __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
     for (int64_t m = a; m <= b; ++m) ok = ok && S.frame_ok[m] != 0;
   }
   r.valid = ok ? 1 : 0;
-  r.pad = 0;
-  drec[(size_t)s * nf + fl] = r;
   const int64_t num = J.sub_start + f * (int64_t)J.N + (int64_t)(J.N / 2);
   const double t = (double)num / J.fs;
+  double d1, d2;
+  poly_derivs(S.delay_poly, S.poly_deg, t, d1, d2);
+  r.rate = (float)d1;
+  drec[(size_t)s * nf + fl] = r;
   for (int sb = 0; sb < J.n_subbands; ++sb)
     prec[((size_t)s * J.n_subbands + sb) * nf + fl] = frame_phase(S, J, sb, t);
 }

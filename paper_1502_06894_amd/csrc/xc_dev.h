@@ -24,6 +24,7 @@ struct DevStation {
   int64_t first_sample;
   int32_t poly_deg;
   int32_t has_phase;          // phase polynomials present for every subband
+  int32_t rate_correct;       // correct the delay's drift inside each frame
   double delay_poly[kMaxPolyDeg + 1];
   const double* phase_poly;   // [n_subbands][kMaxPolyDeg + 1] or nullptr
 };
@@ -49,7 +50,7 @@ struct DelayRec {
   double d;
   int64_t base;
   int32_t valid;
-  int32_t pad;
+  float rate;     // delay rate tau' at the frame centre (s/s): the drift correction's rho
 };
 
 // Per (station, subband, block frame): fringe phase Taylor terms about the

@@ -26,7 +26,13 @@ constexpr int kOutF16 = 1;   // (Re, Im) FP16, scaled by 2^scale_exp
 constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, saturated at 448
 inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
 
-// waves: occupancy target of the F kernel (0 = compiler's choice, else 3..4; FP32 output only).
+// waves: F-stage variant (0 = default; 2..5 as the tuning field describes; FP32 output only
+// except 5).  kFstageRatePass: the drift-correction pass, run after the regular F stage on
+// the stations that ask for it: it transforms the ramp-weighted window and rewrites their
+// spectra in place as (1 - rho) Y + (2 pi i rho k / N) fd Yr (FP32 spectra, N <= 16384; it
+// takes the next task counter, ctr + 1 of the regular pass).
+constexpr int kFstageRatePass = 6;
+constexpr int kMaxRateCorrectN = 16384;   // the drift correction runs in the one-workgroup FFT
 // ctr: task counter, zero at launch (launch_delays clears it), one per concurrent launch.
 // scratch: fstage_scratch_bytes(...) of device memory (N = 32768 only; else unused).
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,

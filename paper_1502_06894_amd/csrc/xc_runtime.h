@@ -121,6 +121,8 @@ int upload_desc(xc_ctx* c, const xc_setup* s, const xc_station* st, const Layout
 // Enqueue every kernel of one job (ingest .. finalise) on `stream`; with two
 // block buffers and `xs` given, the X stages run on `xs` (joined back to
 // `stream` before the finalise).
+// Does any station ask for the drift correction inside frames?
+bool any_rate_correct(const xc_setup* s, const xc_station* st);
 int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_output* out,
                 const DevJob* dj, unsigned char* arena, const Layout& L, const xc_tuning& tu,
                 hipStream_t stream, hipStream_t xs = nullptr);

@@ -110,8 +110,20 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st) {
     for (int k = 0; k <= x.poly_deg; ++k)
       if (!isfinite(x.delay_poly[k]))
         return fail(c, XC_E_INVAL, "station %d: delay_poly[%d] not finite", i, k);
+    if (x.rate_correct != 0 && x.rate_correct != 1)
+      return fail(c, XC_E_INVAL, "station %d: rate_correct=%d", i, x.rate_correct);
+    if (x.rate_correct && (s->precision != XC_FP32 || N > kMaxRateCorrectN))
+      return fail(c, XC_E_INVAL,
+                  "station %d: the drift correction needs the FP32 path and n_chan <= %d", i,
+                  kMaxRateCorrectN / 2);
   }
   return XC_OK;
+}
+
+bool any_rate_correct(const xc_setup* s, const xc_station* st) {
+  for (int i = 0; i < s->n_stations; ++i)
+    if (st[i].rate_correct) return true;
+  return false;
 }
 
 Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, bool overlap) {
@@ -202,6 +214,7 @@ void build_desc(const xc_setup* s, const xc_station* st, const Layout& L,
     d.poly_deg = st[i].poly_deg;
     for (int k = 0; k <= st[i].poly_deg; ++k) d.delay_poly[k] = st[i].delay_poly[k];
     d.has_phase = st[i].phase_poly ? 1 : 0;
+    d.rate_correct = st[i].rate_correct ? 1 : 0;
     d.phase_poly = st[i].phase_poly ? dp + (size_t)i * nsb * (kMaxPolyDeg + 1) : nullptr;
     if (st[i].phase_poly)
       for (int b = 0; b < nsb; ++b)
@@ -234,6 +247,7 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
   PhaseRec* prec = reinterpret_cast<PhaseRec*>(arena + L.prec);
   void* spec = arena + L.spec;
   const bool overlap = L.nbuf == 2 && xs != nullptr;
+  const bool rate_pass = any_rate_correct(s, st);
   double2* vacc = reinterpret_cast<double2*>(arena + L.vacc);
   double* wacc = reinterpret_cast<double*>(arena + L.wacc);
   int8_t* sexp = reinterpret_cast<int8_t*>(arena + L.sexp);
@@ -294,6 +308,14 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
                            reinterpret_cast<float2*>(arena + L.scratch), stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
+    if (rate_pass) {
+      e = timed(c, XC_K_FSTAGE, stream, [&] {
+        return launch_fstage(N, dj, S, nsb * s->n_pols, drec_p, prec_p, c->d_tw, spec_p, sexp,
+                             nf, kFstageRatePass, L.out, ctr_p + 1,
+                             reinterpret_cast<float2*>(arena + L.scratch), stream);
+      });
+      if (e != hipSuccess) return hip_fail(c, e, "fstage drift correction");
+    }
     if (overlap) {
       e = hipEventRecord(c->blk_f[p], stream);
       if (e == hipSuccess) e = hipStreamWaitEvent(xs, c->blk_f[p], 0);
@@ -664,6 +686,10 @@ int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t
   if (e == hipSuccess)
     e = launch_fstage(2 * s->n_chan, dj, s->n_stations, s->n_subbands * s->n_pols, drec, prec,
                       c->d_tw, spectra, nullptr, n, p.tu.fstage_waves_per_simd, kOutF32, ctr,
+                      reinterpret_cast<float2*>(p.arena + p.L.scratch), stream);
+  if (e == hipSuccess && any_rate_correct(s, st))
+    e = launch_fstage(2 * s->n_chan, dj, s->n_stations, s->n_subbands * s->n_pols, drec, prec,
+                      c->d_tw, spectra, nullptr, n, kFstageRatePass, kOutF32, ctr + 1,
                       reinterpret_cast<float2*>(p.arena + p.L.scratch), stream);
   return e == hipSuccess ? XC_OK : hip_fail(c, e, "debug_spectra");
 }

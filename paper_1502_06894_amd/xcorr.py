@@ -37,7 +37,7 @@ class XcStation(C.Structure):
                 ("first_sample", C.c_int64), ("frame_ok", C.c_void_p),
                 ("poly_deg", C.c_int32), ("delay_poly", C.POINTER(C.c_double)),
                 ("phase_poly", C.POINTER(C.c_double)), ("poly_t0", C.c_double),
-                ("poly_t1", C.c_double)]
+                ("poly_t1", C.c_double), ("rate_correct", C.c_int32)]
 
 
 class XcOutput(C.Structure):
@@ -177,7 +177,8 @@ class _Marshal:
                 ok = frame_ok[i].data_ptr()
             arr[i] = XcStation(fr.data_ptr(), fr.shape[0], int(st.first_sample), ok,
                                dp.shape[0] - 1, dp.ctypes.data_as(C.POINTER(C.c_double)),
-                               pp_ptr, float(st.poly_span[0]), float(st.poly_span[1]))
+                               pp_ptr, float(st.poly_span[0]), float(st.poly_span[1]),
+                               int(bool(getattr(st, "rate_correct", False))))
         self.stations = arr
 
 

@@ -45,6 +45,7 @@ int main(void) {
   F(xc_station, frames); F(xc_station, n_frames_m5b); F(xc_station, first_sample);
   F(xc_station, frame_ok); F(xc_station, poly_deg); F(xc_station, delay_poly);
   F(xc_station, phase_poly); F(xc_station, poly_t0); F(xc_station, poly_t1);
+  F(xc_station, rate_correct);
   F(xc_output, vis); F(xc_output, weight);
   printf("xc_tuning %zu\nxc_job %zu\nxc_server_stats %zu\n", sizeof(xc_tuning),
          sizeof(xc_job), sizeof(xc_server_stats));

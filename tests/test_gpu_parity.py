@@ -189,6 +189,46 @@ def test_perigee_acceleration_parity(xc, corr, tau2):
     assert rel_l2(vis.cpu().numpy(), V) < TOL
 
 
+@pytest.mark.parametrize("rate,n_chan", [(3e-5, 2048), (3e-4, 512), (3e-5, 8192)])
+def test_drift_correction_parity(xc, corr, rate, n_chan):
+    """Intra-frame delay-drift correction (O11) on the space station: spectra and
+    visibilities against the oracle, and the correction is not a no-op."""
+    import dataclasses
+    from synth import shape
+    fs, t0 = configs.FS_16MHZ, configs.SUB_START_S
+    ground = [0.011, -2e-6, 0.0]
+    space = [0.08 - rate * t0, rate, 0.0]
+    job = shape.build_job(n_stations=2, n_subbands=2, n_pols=1, n_chan=n_chan, C=2, fs=fs,
+                          lo_hz=[configs.LO0_HZ, configs.LO0_HZ + 16e6],
+                          sub_start=int(t0 * fs), n_frames=12, delay_polys=[ground, space],
+                          shifts=[0, 0], phase_zero=False, seed=93, margin=4096)
+    off = job
+    job = dataclasses.replace(job, stations=[job.stations[0],
+                                             dataclasses.replace(job.stations[1], rate_correct=True)])
+    Y = fx.station_spectra(job, 1, 1, 0, np.arange(12))[0]
+    Y0 = fx.station_spectra(off, 1, 1, 0, np.arange(12))[0]
+    assert rel_l2(Y0, Y) > 1e-4 * rate / 3e-5          # the correction changes the spectra
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    spec = corr.debug_spectra(job, 0, 12).cpu().numpy()
+    assert rel_l2(spec[1, :, 1, :], Y) < 3e-6
+    assert rel_l2(spec[1, :, 0, :], fx.station_spectra(job, 0, 1, 0, np.arange(12))[0]) < 3e-6
+    vis, w = corr.correlate(job)
+    assert np.array_equal(w.cpu().numpy(), W.astype(np.float32))
+    assert rel_l2(vis.cpu().numpy(), V) < TOL
+
+
+def test_drift_correction_limits(xc, corr):
+    import dataclasses
+    job = configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=8)
+    job = dataclasses.replace(job, stations=[dataclasses.replace(job.stations[0], rate_correct=True),
+                                             job.stations[1]])
+    _on_gpu(xc, job)
+    with pytest.raises(xc.XcError) as e:
+        corr.correlate(job, precision=xc.XC_FP16_MFMA)
+    assert e.value.code == xc.XC_E_INVAL
+
+
 def test_bad_frames_and_out_of_buffer(xc, corr):
     job = configs.small_job(n_stations=3, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=400,
                             realistic=False, seed=5)
