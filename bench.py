@@ -112,7 +112,8 @@ def cpu_baseline(job, budget_s: float = 12.0, max_frames: int = 8192):
         hi = min(st.n_frames_m5b, (int(base.max()) + job.N) // spf + 2)
         stations.append(Station(frames=st.frames[lo:hi].cpu(), first_sample=st.first_sample + lo * spf,
                                 delay_poly=st.delay_poly, phase_poly=st.phase_poly,
-                                poly_span=st.poly_span, station_id=st.station_id))
+                                poly_span=st.poly_span, station_id=st.station_id,
+                                rate_correct=st.rate_correct))
     sub = Job(n_stations=job.n_stations, n_subbands=job.n_subbands, n_pols=job.n_pols,
               n_chan=job.n_chan, n_streams=job.n_streams, stream_map=job.stream_map,
               fs_hz=job.fs_hz, lo_hz=job.lo_hz, sub_start=job.sub_start, n_frames=max_frames,
@@ -511,6 +512,8 @@ def main():
     ap.add_argument("--frames", type=int, default=0,
                     help="shorten the sub-integration (profiling runs only; not a bench figure)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate-correct", action="store_true",
+                    help="c1/c2: correct the space station's delay drift inside frames")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--rocpd-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
@@ -547,6 +550,13 @@ def main():
     log(f"generating workload {a.workload} on the GPU")
     t = time.perf_counter()
     job, desc = make_job(a.workload, a.frames)
+    if a.rate_correct:
+        import dataclasses
+        # the delay-drift correction on the space station (station 0)
+        job = dataclasses.replace(job, stations=[dataclasses.replace(job.stations[0],
+                                                                     rate_correct=True)]
+                                  + list(job.stations[1:]))
+        desc += "; delay-drift correction on the space station"
     xcorr.job_to_device(job, "cuda:0")
     torch.cuda.synchronize()
     log(f"workload ready in {time.perf_counter() - t:.1f} s: {job.station_samples:.3e} "

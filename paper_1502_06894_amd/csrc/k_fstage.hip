@@ -133,7 +133,9 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // W = kFstageRatePass: the drift-correction pass over the stations that ask
   // for it: the window is weighted by the ramp (n - N/2) before the transform,
   // and the stored spectrum Y (from the regular pass) becomes
-  // (1 - rho) Y + (2 pi i rho k / N) fd Yr
+  // (1 - rho) Y + (2 pi i rho k / N) fd Yr.  Its tasks are (flagged station,
+  // frame group, input), finer than the regular (station, frame group), so
+  // that the few flagged stations still spread evenly over the workgroups.
   constexpr bool kRamp = W == kFstageRatePass;
   static_assert(!kRamp || OUT == kOutF32, "the drift correction rewrites FP32 spectra");
   extern __shared__ float2 lds_all[];
@@ -141,7 +143,13 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   const int g = threadIdx.x / T, t = threadIdx.x % T;
   const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
   const int n_groups = (nf + G - 1) / G;
-  const int n_tasks = n_groups * J.n_stations;
+  int n_flag = J.n_stations;
+  if constexpr (kRamp) {
+    n_flag = 0;
+    for (int i = 0; i < J.n_stations; ++i) n_flag += J.st[i].rate_correct ? 1 : 0;
+  }
+  const int per_station = kRamp ? n_groups * J.n_inputs : n_groups;
+  const int n_tasks = per_station * n_flag;
 
   float2* lds = lds_all + g * lds_words<N>();
   // 2-bit code -> level (offset binary: -3.3359, -1, +1, +3.3359), and four
@@ -162,9 +170,29 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // With whole waves per frame (T >= 64) the frame index is wave-uniform: the
   // delay and phase records then come in through scalar loads, which a wave
   // does not have to order behind its own outstanding spectrum stores.
-  auto frame_of = [&](int task, int& st, int& fl) {
-    st = task / n_groups;
-    fl = (task - st * n_groups) * G + g;
+  auto frame_of = [&](int task, int& st, int& fl, int& in) {
+    if (task >= n_tasks) {   // a workgroup beyond the tasks: an empty, invalid record
+      st = 0;
+      fl = nf;
+      in = 0;
+      return;
+    }
+    st = task / per_station;
+    int grp = task - st * per_station;
+    in = 0;
+    if constexpr (kRamp) {
+      in = grp % J.n_inputs;
+      grp /= J.n_inputs;
+      // the st-th station that asks for the correction
+      for (int i = 0, k = -1; i < J.n_stations; ++i) {
+        k += J.st[i].rate_correct ? 1 : 0;
+        if (k == st && J.st[i].rate_correct) {
+          st = i;
+          break;
+        }
+      }
+    }
+    fl = grp * G + g;
     if (T >= 64) fl = __builtin_amdgcn_readfirstlane(fl);
   };
   auto record_of = [&](int st, int fl) {
@@ -180,8 +208,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   };
 
   int task = blockIdx.x;
-  int s = 0, fl = 0;
-  frame_of(task, s, fl);
+  int s = 0, fl = 0, in_t = 0;
+  frame_of(task, s, fl, in_t);
   DelayRec r = record_of(s, fl);
   uint32_t wv[E];
   int sh0;
@@ -196,8 +224,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     if (threadIdx.x == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
     __syncthreads();
     const int task_n = next_task;   // rewritten only after the input loop's barriers
-    int s_n = 0, fl_n = nf;
-    if (task_n < n_tasks) frame_of(task_n, s_n, fl_n);
+    int s_n = 0, fl_n = nf, in_n = 0;
+    if (task_n < n_tasks) frame_of(task_n, s_n, fl_n, in_n);
     const DelayRec r_n = record_of(s_n, fl_n);
     uint32_t wv_n[kPrefetch ? E : 1];
     int sh0_n = 0;
@@ -223,10 +251,9 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
 
     // the fringe phasors of a subband, kept for its second pol when kShare
     float2 zs[E];
-    // (the drift-correction pass skips the stations that do not ask for it; the
-    // station is the same for the whole workgroup)
-    const int n_in = kRamp && !J.st[s].rate_correct ? 0 : J.n_inputs;
-    for (int in = 0; in < n_in; ++in) {
+    // (a drift-correction task is one input)
+    const int in_lo = kRamp ? in_t : 0, in_hi = kRamp ? in_t + 1 : J.n_inputs;
+    for (int in = in_lo; in < in_hi; ++in) {
       const int sb = in / P, p = in - sb * P;
       const int sh = sh0 + 2 * J.stream_map[in];
       if (!kShare || p == 0) {
@@ -304,6 +331,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     task = task_n;
     s = s_n;
     fl = fl_n;
+    in_t = in_n;
     r = r_n;
     if constexpr (kPrefetch) {
       sh0 = sh0_n;
