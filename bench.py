@@ -580,7 +580,7 @@ def main():
           for _ in range(a.steps)]
     T = a.frames_per_block or min(2048, job.n_frames)
     blocks = -(-job.n_frames // T)
-    corr.profile_begin(max_launches=a.steps * (3 * blocks + 4) + 16)
+    corr.profile_begin(max_launches=a.steps * (4 * blocks + 4) + 16)   # delays, F (+ drift pass), X
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
