@@ -180,13 +180,22 @@ int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
  * which rounds the FFT's last-pass twiddles differently (results stay within
  * the FP32 path's tolerance). */
 typedef struct {
-  int32_t fstage_waves_per_simd;   /* F-stage variant: 0 or 1 = default; 2 = the pols of a
-                                      subband share their fringe phasors (fewer operations,
-                                      more registers); 3 or 4 = at least that many waves per
+  int32_t fstage_waves_per_simd;   /* F-stage variant: 0 = default (7 for FFT lengths of
+                                      8192 and more, else 1); 1 = one task per station and
+                                      frame group, the next task's window words loaded
+                                      during the transforms; 2 = the pols of a subband
+                                      share their fringe phasors (fewer operations, more
+                                      registers); 3 or 4 = at least that many waves per
                                       SIMD requested (fewer registers); 5 = split twiddle
                                       tables (the last FFT pass multiplies two table
                                       entries: less LDS per workgroup, so more resident
-                                      workgroups, for one complex multiply per twiddle) */
+                                      workgroups, for one complex multiply per twiddle);
+                                      7 = lean tasks: one per station, frame group and
+                                      group of up to four inputs, whose 2-bit codes are
+                                      packed into one register per input before the
+                                      transforms (split twiddles, 4 waves per SIMD; the
+                                      window words are loaded once per group).  2-4
+                                      apply to FP32 spectra only. */
   int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
                                       stages filled by direct memory-to-LDS loads (64-channel
                                       tiles, at most 32 inputs per subband; the default where

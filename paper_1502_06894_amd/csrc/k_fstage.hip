@@ -40,7 +40,7 @@ struct FGeom {
 // Twiddle source of k_fstage<N, W, ...>: W = 5 selects the split tables.
 template <int N, int W>
 constexpr int fstage_twm() {
-  return W == 5 && N >= 512 ? kTwSplit : tw_default<N>();
+  return (W == 5 || W == kFstageLean) && N >= 512 ? kTwSplit : tw_default<N>();
 }
 
 // Spectrum element written by the F stage: FP32 complex, or for the MFMA X
@@ -115,7 +115,7 @@ __device__ inline void load_window(const DevJob& J, int s, const DelayRec& r, in
 // outputs `scale_exp` [n_sb][M][n_chan] holds the power-of-two exponents.
 template <int N, int W, int OUT>
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
-                               amdgpu_waves_per_eu(W == 3 || W == 4 ? W : 1)))
+                               amdgpu_waves_per_eu(W == 3 || W == 4 ? W : W == kFstageLean ? 4 : 1)))
     k_fstage(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
              void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf,
@@ -137,6 +137,11 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // frame group, input), finer than the regular (station, frame group), so
   // that the few flagged stations still spread evenly over the workgroups.
   constexpr bool kRamp = W == kFstageRatePass;
+  // W = kFstageLean: tasks (station, frame group, group of up to kLeanGroup
+  // inputs); the group's codes are packed before the transforms, the words are
+  // loaded per task (no prefetch) and the fractional-delay phasors are stepped
+  // at the store instead of held in registers.  Asks for 4 waves per SIMD.
+  constexpr bool kLean = W == kFstageLean;
   static_assert(!kRamp || OUT == kOutF32, "the drift correction rewrites FP32 spectra");
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
@@ -148,7 +153,9 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     n_flag = 0;
     for (int i = 0; i < J.n_stations; ++i) n_flag += J.st[i].rate_correct ? 1 : 0;
   }
-  const int per_station = kRamp ? n_groups * J.n_inputs : n_groups;
+  const int n_igroups = kRamp ? J.n_inputs
+                              : kLean ? (J.n_inputs + kLeanGroup - 1) / kLeanGroup : 1;
+  const int per_station = n_groups * n_igroups;
   const int n_tasks = per_station * n_flag;
 
   float2* lds = lds_all + g * lds_words<N>();
@@ -180,6 +187,10 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     st = task / per_station;
     int grp = task - st * per_station;
     in = 0;
+    if constexpr (kLean) {
+      in = grp % n_igroups;
+      grp /= n_igroups;
+    }
     if constexpr (kRamp) {
       in = grp % J.n_inputs;
       grp /= J.n_inputs;
@@ -219,7 +230,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
 
   // The next task's words are loaded while this task is transformed, except
   // for N = 16384 (1024 threads, 128 registers each: no room for them).
-  constexpr bool kPrefetch = N <= 8192;
+  constexpr bool kPrefetch = N <= 8192 && !kLean;
   while (task < n_tasks) {
     if (threadIdx.x == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
     __syncthreads();
@@ -237,25 +248,49 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     // fractional-delay phasors of this thread's kept output bins
     // k = t + b T + r N/16 (b < BL, r < 8): exp(2 pi i k d / N) =
     // exp(2 pi i (t + b T) d / N) * exp(2 pi i d / 16)^r
-    float2 fd[BL][8];
+    constexpr int FDK = kLean ? 1 : 8;
+    float2 fd[BL][FDK];
+    float2 fd_st;
     {
       const float dd = (float)r.d;
-      const float2 st = phasor_turns(dd * (1.0f / 16.0f));
+      fd_st = phasor_turns(dd * (1.0f / 16.0f));
 #pragma unroll
       for (int b = 0; b < BL; ++b) {
         fd[b][0] = phasor_turns((float)(t + b * T) * dd * (1.0f / (float)N));
 #pragma unroll
-        for (int rr = 1; rr < 8; ++rr) fd[b][rr] = cmul(fd[b][rr - 1], st);
+        for (int rr = 1; rr < FDK; ++rr) fd[b][rr] = cmul(fd[b][rr - 1], fd_st);
       }
     }
 
     // the fringe phasors of a subband, kept for its second pol when kShare
     float2 zs[E];
-    // (a drift-correction task is one input)
-    const int in_lo = kRamp ? in_t : 0, in_hi = kRamp ? in_t + 1 : J.n_inputs;
+    // (a drift-correction task is one input, a lean task a group of inputs)
+    const int in_lo = kRamp ? in_t : kLean ? in_t * kLeanGroup : 0;
+    const int in_hi = kRamp ? in_t + 1
+                            : kLean ? min(in_lo + kLeanGroup, J.n_inputs) : J.n_inputs;
+    // lean: the group's 2-bit codes, 16 per input packed in one register, so
+    // that the window words are not held across the transforms
+    uint32_t codes[kLean ? kLeanGroup : 1];
+    if constexpr (kLean) {
+#pragma unroll
+      for (int i = 0; i < kLeanGroup; ++i) {
+        const int sh = sh0 + 2 * J.stream_map[min(in_lo + i, in_hi - 1)];
+        uint32_t c = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) c |= ((wv[e] >> sh) & 3u) << (2 * e);
+        codes[i] = c;
+      }
+    }
     for (int in = in_lo; in < in_hi; ++in) {
       const int sb = in / P, p = in - sb * P;
       const int sh = sh0 + 2 * J.stream_map[in];
+      uint32_t code_in = 0;
+      if constexpr (kLean) {
+        const int i = in - in_lo;
+        code_in = codes[0];
+#pragma unroll
+        for (int j = 1; j < kLeanGroup; ++j) code_in = i == j ? codes[j] : code_in;
+      }
       if (!kShare || p == 0) {
         PhaseRec ph;
         if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
@@ -294,7 +329,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
       float2 v[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        float q = lut_t[(wv[e] >> sh) & 3u];
+        float q = kLean ? lut_t[(code_in >> (2 * e)) & 3u] : lut_t[(wv[e] >> sh) & 3u];
         if constexpr (kRamp) q *= (float)(t + e * T - N / 2);
         v[e] = make_float2(q * zs[e].x, q * zs[e].y);
       }
@@ -308,23 +343,30 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
         const int8_t* ex = OUT == kOutF32 ? nullptr
                                           : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
 #pragma unroll
-        for (int b = 0; b < BL; ++b)
+        for (int b = 0; b < BL; ++b) {
+          float2 fdr = fd[b][0];
 #pragma unroll
           for (int rr = 0; rr < 8; ++rr) {
             const int k = t + b * T + rr * (N / 16);
+            if constexpr (kLean) {
+              if (rr > 0) fdr = cmul(fdr, fd_st);
+            } else {
+              fdr = fd[b][rr];
+            }
             if constexpr (kRamp) {
               float2* sp = static_cast<float2*>(spec) + row + k;
               if (valid) {
                 const float2 old = *sp;
-                const float2 yr = cmul(v[b + rr * BL], fd[b][rr]);
+                const float2 yr = cmul(v[b + rr * BL], fdr);
                 const float rho = r.rate, a = 6.28318530717958648f * rho * (float)k / (float)N;
                 *sp = make_float2((1.0f - rho) * old.x - a * yr.y, (1.0f - rho) * old.y + a * yr.x);
               }
             } else {
-              const float2 y = valid ? cmul(v[b + rr * BL], fd[b][rr]) : make_float2(0.f, 0.f);
+              const float2 y = valid ? cmul(v[b + rr * BL], fdr) : make_float2(0.f, 0.f);
               put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
             }
           }
+        }
       }
       __syncthreads();   // the next input reuses lds
     }
@@ -372,21 +414,40 @@ static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* d
   return hipGetLastError();
 }
 
+// Lean tasks per frame group: one per group of up to kLeanGroup inputs of each
+// station (what launch_nw sizes the grid by in place of the station count).
+static inline int lean_units(int n_stations, int n_inputs) {
+  return n_stations * ((n_inputs + kLeanGroup - 1) / kLeanGroup);
+}
+
+template <int N, int OUT>
+static hipError_t launch_lp(const DevJob* job, int n_stations, int n_inputs, const DelayRec* drec,
+                            const PhaseRec* prec, const float2* tw, void* spec,
+                            const int8_t* scale_exp, int nf, int waves, unsigned* ctr,
+                            hipStream_t s) {
+  if (waves == 5)
+    return launch_nw<N, 5, OUT>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
+  if (waves == kFstageLean)
+    return launch_nw<N, kFstageLean, OUT>(job, lean_units(n_stations, n_inputs), drec, prec, tw,
+                                          spec, scale_exp, nf, ctr, s);
+  return launch_nw<N, 0, OUT>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, ctr, s);
+}
+
 template <int N>
-static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* drec,
+static hipError_t launch_n(const DevJob* job, int n_stations, int n_inputs, const DelayRec* drec,
                            const PhaseRec* prec, const float2* tw, void* spec,
                            const int8_t* scale_exp, int nf, int waves, int out, unsigned* ctr,
                            hipStream_t s) {
+  // the default: lean tasks where the transform is large enough for them to pay
+  // (measured on MI355X, F stage of C4-shaped jobs: -15 % at N = 8192, -13 % at
+  // 16384; at 4096 -3 % there but +1.5 % over a mix of uneven jobs; +3 % at 2048)
+  if (waves == 0 && N >= kLeanMinN) waves = kFstageLean;
   if (out == kOutF16)
-    return waves == 5 ? launch_nw<N, 5, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp,
-                                                 nf, ctr, s)
-                      : launch_nw<N, 0, kOutF16>(job, n_stations, drec, prec, tw, spec, scale_exp,
-                                                 nf, ctr, s);
+    return launch_lp<N, kOutF16>(job, n_stations, n_inputs, drec, prec, tw, spec, scale_exp, nf,
+                                 waves, ctr, s);
   if (out == kOutF8)
-    return waves == 5 ? launch_nw<N, 5, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp,
-                                                nf, ctr, s)
-                      : launch_nw<N, 0, kOutF8>(job, n_stations, drec, prec, tw, spec, scale_exp,
-                                                nf, ctr, s);
+    return launch_lp<N, kOutF8>(job, n_stations, n_inputs, drec, prec, tw, spec, scale_exp, nf,
+                                waves, ctr, s);
   switch (waves) {
     case 2:
       return launch_nw<N, 2, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
@@ -396,6 +457,9 @@ static hipError_t launch_n(const DevJob* job, int n_stations, const DelayRec* dr
       return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     case 5:
       return launch_nw<N, 5, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
+    case kFstageLean:
+      return launch_nw<N, kFstageLean, kOutF32>(job, lean_units(n_stations, n_inputs), drec, prec,
+                                                tw, spec, nullptr, nf, ctr, s);
     case kFstageRatePass:
       if constexpr (N <= kMaxRateCorrectN)
         return launch_nw<N, kFstageRatePass, kOutF32>(job, n_stations, drec, prec, tw, spec,
@@ -570,7 +634,8 @@ hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,
   switch (N) {
 #define XC_FCASE(NN)                                                                      \
   case NN:                                                                                \
-    return launch_n<NN>(job, n_stations, drec, prec, tw, spec, scale_exp, nf, waves, out, ctr, s);
+    return launch_n<NN>(job, n_stations, n_inputs, drec, prec, tw, spec, scale_exp, nf, waves, \
+                        out, ctr, s);
     XC_FCASE(256) XC_FCASE(512) XC_FCASE(1024) XC_FCASE(2048) XC_FCASE(4096) XC_FCASE(8192)
     XC_FCASE(16384)
 #undef XC_FCASE

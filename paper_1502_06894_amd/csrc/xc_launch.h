@@ -26,12 +26,19 @@ constexpr int kOutF16 = 1;   // (Re, Im) FP16, scaled by 2^scale_exp
 constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, saturated at 448
 inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
 
-// waves: F-stage variant (0 = default; 2..5 as the tuning field describes; FP32 output only
-// except 5).  kFstageRatePass: the drift-correction pass, run after the regular F stage on
+// waves: F-stage variant (0 = default: kFstageLean for N >= kLeanMinN, else one task per
+// station and frame group; 1 = the latter at every N; 2..5, 7 as the tuning field describes;
+// FP32 output only except 5 and 7).  kFstageLean: tasks of up to four inputs whose 2-bit
+// codes are packed into one register each, so the window words are not held across the
+// transforms (fewer registers, more resident waves, for reloading the words per group).
+// kFstageRatePass: the drift-correction pass, run after the regular F stage on
 // the stations that ask for it: it transforms the ramp-weighted window and rewrites their
 // spectra in place as (1 - rho) Y + (2 pi i rho k / N) fd Yr (FP32 spectra, N <= 16384; it
 // takes the next task counter, ctr + 1 of the regular pass).
 constexpr int kFstageRatePass = 6;
+constexpr int kFstageLean = 7;
+constexpr int kLeanMinN = 8192;
+constexpr int kLeanGroup = 4;   // inputs per lean task
 constexpr int kMaxRateCorrectN = 16384;   // the drift correction runs in the one-workgroup FFT
 // ctr: task counter, zero at launch (launch_delays clears it), one per concurrent launch.
 // scratch: fstage_scratch_bytes(...) of device memory (N = 32768 only; else unused).

@@ -547,7 +547,8 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
 
 int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
   if (!c || !t) return XC_E_INVAL;
-  const bool ok = t->fstage_waves_per_simd >= 0 && t->fstage_waves_per_simd <= 5 &&
+  const bool ok = t->fstage_waves_per_simd >= 0 &&
+                  (t->fstage_waves_per_simd <= 5 || t->fstage_waves_per_simd == kFstageLean) &&
                   (t->xmac_frames_per_stage == 0 || t->xmac_frames_per_stage == 1 ||
                    t->xmac_frames_per_stage == 2 || t->xmac_frames_per_stage == 4 ||
                    t->xmac_frames_per_stage == 8) &&

@@ -135,6 +135,41 @@ def test_split_twiddles_parity(xc, corr, n_chan, C):
     assert rel_l2(vis, V) < TOL
 
 
+@pytest.mark.parametrize("n_chan,C,nsb,P,variant", [
+    (1024, 16, 3, 2, 7),     # six inputs: a group of four and one of two
+    (128, 4, 1, 1, 7),       # one input; 16 frames per workgroup
+    (4096, 8, 5, 1, 0),      # the default at N = 8192 (lean): groups of four and one
+    (8192, 16, 9, 1, 0),     # the default at N = 16384: groups 4 + 4 + 1
+    (2048, 4, 2, 2, 7),      # lean at N = 4096, four inputs: one group
+    (4096, 8, 5, 1, 1),      # one task per station and frame group at N = 8192
+], ids=["lean2048_6in", "lean256_1in", "default8192_5in", "default16384_9in", "lean4096_4in",
+        "classic8192"])
+def test_fstage_task_shapes_parity(xc, corr, n_chan, C, nsb, P, variant):
+    """F-stage task shapes (one task per station and frame group, or the lean
+    tasks over groups of up to four inputs with packed codes): spectra within
+    the F stage's bound of the oracle for every input, visibilities within TOL."""
+    job = configs.small_job(n_stations=3, n_subbands=nsb, n_pols=P, n_chan=n_chan, C=C,
+                            n_frames=7, seed=n_chan + 3 * nsb + P)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    try:
+        corr.set_tuning(fstage_waves_per_simd=variant)
+        spec = corr.debug_spectra(job, 0, 7).cpu().numpy()
+        vis, w = corr.correlate(job)
+        vis = vis.cpu().numpy()
+    finally:
+        corr.set_tuning(fstage_waves_per_simd=0)
+    for s in range(3):
+        for sb in range(nsb):
+            for p in range(P):
+                Y = fx.station_spectra(job, s, sb, p, np.arange(7))[0]
+                assert rel_l2(spec[sb, :, s * P + p, :], Y) < 3e-6, (s, sb, p)
+    assert np.array_equal(w.cpu().numpy(), W.astype(np.float32))
+    for sb in range(nsb):
+        for bl in range(job.n_baselines):
+            assert rel_l2(vis[sb, bl], V[sb, bl]) < TOL, (sb, bl)
+
+
 VIS_CASES = [
     # name, small_job kwargs, frames_per_block
     ("c1like", dict(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=300), 0),

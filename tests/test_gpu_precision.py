@@ -49,16 +49,23 @@ def _norm_err(vis, V, job):
     return worst, rows
 
 
+def _c4_shaped():
+    # the C4 geometry (32 stations, 64 Msps, N = 8192, 4096 channels) over 96 frames
+    return configs.c4_job(n_frames=96, n_subbands=1)
+
+
 @pytest.mark.parametrize("prec", ["fp16", "fp8"])
 @pytest.mark.parametrize("kw", [
     dict(n_stations=32, n_subbands=2, n_pols=1, n_chan=512, C=4, n_frames=96, realistic=False),
     dict(n_stations=6, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=75),
-], ids=["m32", "dualpol"])
+    None,
+], ids=["m32", "dualpol", "c4shape"])
 def test_mfma_precision_bound(xc, corr, prec, kw):
-    job = configs.small_job(**kw, seed=17)
+    job = _c4_shaped() if kw is None else configs.small_job(**kw, seed=17)
     V, W = fx.correlate(job, threads=8)
     xc.job_to_device(job)
-    vis, w = corr.correlate(job, precision=xc.PRECISIONS[prec], frames_per_block=64)
+    fpb = 64 if kw is not None else 0
+    vis, w = corr.correlate(job, precision=xc.PRECISIONS[prec], frames_per_block=fpb)
     torch.cuda.synchronize()
     vis, w = vis.cpu().numpy(), w.cpu().numpy()
     assert np.array_equal(w, W.astype(np.float32))
@@ -66,8 +73,13 @@ def test_mfma_precision_bound(xc, corr, prec, kw):
     u = U[prec]
     bound = 1.1 * (2 * u + u * u)
     rel = np.array([r[4] for r in rows])
-    print(f"\n{prec} {job.M} inputs: max |dV|/sqrt(AiAj) = {worst:.3e} (bound {bound:.3e}); "
-          f"per-baseline relative L2: median {np.median(rel):.3e}, max {rel.max():.3e}")
+    auto = np.array([r[3] for r in rows if r[1] == r[2]])
+    cross = np.array([r[3] for r in rows if r[1] != r[2]])
+    print(f"\n{prec} {job.M} inputs, {job.n_chan} channels: max |dV|/sqrt(AiAj) = {worst:.3e} "
+          f"(bound {bound:.3e}); per baseline max over channels: autos median "
+          f"{np.median(auto):.3e} max {auto.max():.3e}, crosses median {np.median(cross):.3e} "
+          f"max {cross.max():.3e}; per-baseline relative L2: median {np.median(rel):.3e}, "
+          f"max {rel.max():.3e}")
     assert worst <= bound
 
 
