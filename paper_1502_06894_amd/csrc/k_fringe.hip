@@ -158,22 +158,43 @@ __global__ void __launch_bounds__(kFringeThreads)
     } else {
       small_dft<R>(v);
     }
-    // v[j] = G[tl + j R/16, d] (FFT), G[j, d] (registers)
-    const int ds = signed_bin(d, D);
-    const bool d_in = delay_win <= 0 || (ds <= delay_win && ds >= -delay_win);
+    // v[j] = G[tl + j R/16, d] (FFT), G[j, d] (registers); r grows with j
+    auto rate_of = [&](int j) { return Rg::fft ? tl + j * (R / 16) : j; };
+    if (map) {
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int r = Rg::fft ? tl + j * (R / 16) : j;
-      const float2 g = v[j];
-      if (map) map[((size_t)map_id * R + r) * D + d] = g;
-      const int rs = signed_bin(r, R);
-      const bool in = d_in && (rate_win <= 0 || (rs <= rate_win && rs >= -rate_win));
-      const float a2 = g.x * g.x + g.y * g.y;
-      const int idx = r * D + d;
-      if (in && better(a2, idx, bv, bi)) {
-        bv = a2;
-        bi = idx;
+      for (int j = 0; j < E; ++j) map[((size_t)map_id * R + rate_of(j)) * D + d] = v[j];
+    }
+    // the round's largest |G|^2 (first j on ties: the smallest index r D + d),
+    // then one comparison with the thread's best under the tie rule
+    float m = -1.f;
+    int mj = 0;
+    if (delay_win <= 0 && rate_win <= 0) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const float a2 = v[j].x * v[j].x + v[j].y * v[j].y;
+        if (a2 > m) {
+          m = a2;
+          mj = j;
+        }
       }
+    } else {
+      const int ds = signed_bin(d, D);
+      const bool d_in = delay_win <= 0 || (ds <= delay_win && ds >= -delay_win);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int rs = signed_bin(rate_of(j), R);
+        const bool in = d_in && (rate_win <= 0 || (rs <= rate_win && rs >= -rate_win));
+        const float a2 = v[j].x * v[j].x + v[j].y * v[j].y;
+        if (in && a2 > m) {
+          m = a2;
+          mj = j;
+        }
+      }
+    }
+    const int idx = rate_of(mj) * D + d;
+    if (m >= 0.f && better(m, idx, bv, bi)) {
+      bv = m;
+      bi = idx;
     }
   };
   // D >= 256 is a multiple of GC (<= 256): every round is full.  Two rounds'
