@@ -201,10 +201,18 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": n, "dispatches": 5}))
 
 
-def _per_job_fpb(job, elem_bytes=8, cap=1 << 30):
-    """Frames per block the batch executor picks (staged spectra capped at 1 GiB)."""
+def _default_fpb(job, elem_bytes=8):
+    """The library's default frames per block: 2048, or up to 65536 while the
+    block's staged spectra stay within 256 MiB."""
     per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
-    T = min(2048, job.n_frames)
+    return int(min(max(2048, min(65536, (256 << 20) // per_frame)), job.n_frames))
+
+
+def _per_job_fpb(job, elem_bytes=8, cap=1 << 30):
+    """Frames per block the batch executor picks: the library default, with the
+    staged spectra capped at 1 GiB."""
+    per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
+    T = _default_fpb(job, elem_bytes)
     if T * per_frame > cap:
         T = max(64, cap // per_frame)
     return int(T)
@@ -578,7 +586,7 @@ def main():
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(a.steps)]
-    T = a.frames_per_block or min(2048, job.n_frames)
+    T = a.frames_per_block or _default_fpb(job)
     blocks = -(-job.n_frames // T)
     corr.profile_begin(max_launches=a.steps * (4 * blocks + 4) + 16)   # delays, F (+ drift pass), X
     torch.cuda.synchronize()
@@ -645,7 +653,7 @@ def main():
         "config": {"workload": desc, "stations": job.n_stations, "subbands": job.n_subbands,
                    "pols": job.n_pols, "channels": job.n_chan, "fft_len": job.N,
                    "frames": job.n_frames, "station_samples_per_step": ss,
-                   "frames_per_block": a.frames_per_block or min(2048, job.n_frames),
+                   "frames_per_block": a.frames_per_block or _default_fpb(job),
                    "precision": "fp32", "parallelism": "single GPU"},
         "roofline": roof,
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),

@@ -97,8 +97,10 @@ typedef struct {
   int64_t sub_start;           /* reference-time sample index of the sub-integration start */
   int64_t n_frames;            /* FFT frames in the sub-integration (>= 1) */
   int32_t precision;           /* XC_FP32 | XC_FP16_MFMA | XC_FP8_MFMA */
-  int32_t frames_per_block;    /* frames staged per F/X round, 0 = library default (2048);
-                                  at most 2048 */
+  int32_t frames_per_block;    /* frames staged per F/X round, at most 65536; 0 = library
+                                  default: 2048, or more (up to 65536) while the block's
+                                  staged spectra stay within 256 MiB, so that small jobs
+                                  run in fewer, larger rounds */
 } xc_setup;
 
 typedef struct {
@@ -204,7 +206,8 @@ typedef struct {
                                       1 = no LDS staging (inputs read from memory, one frame
                                       ahead); 0 = default */
   int32_t xmac_channels_per_wg;    /* X-stage channel tile: 0, 16, 32 or 64 */
-  int32_t frames_per_block;        /* used when a setup says 0: 0 (= 2048) or 1..2048 */
+  int32_t frames_per_block;        /* used when a setup says 0: 0 (= the library default)
+                                      or 1..65536 */
   int32_t xmac_tiles_per_wg;       /* X-stage 4x4 input tiles per workgroup: 0 = all */
   int32_t block_overlap;           /* single-job calls over two or more blocks: 0 = default
                                       (off), 1 = off, 2 = on.  On: the F stage of block b + 1

@@ -77,14 +77,21 @@ hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int6
   return hipGetLastError();
 }
 
-// One workgroup per station pair (si <= sj): count frames valid for both.
+// One workgroup per station pair (si <= sj) and chunk of kWeightChunk frames:
+// count the frames valid for both and add the count to the pair's total.  The
+// counts are integers, exact in FP64 whatever order the chunks add in.
+constexpr int kWeightChunk = 2048;
+
 __global__ void k_weights(const DelayRec* __restrict__ drec, int S, int nf,
                           double* __restrict__ wst) {
   const int si = blockIdx.x, sj = blockIdx.y;
   if (sj < si) return;
+  const int f0 = blockIdx.z * kWeightChunk;
+  const int f1 = nf < f0 + kWeightChunk ? nf : f0 + kWeightChunk;
   __shared__ int part[256];
   int cnt = 0;
-  for (int f = threadIdx.x; f < nf; f += blockDim.x)
+#pragma unroll 8
+  for (int f = f0 + (int)threadIdx.x; f < f1; f += blockDim.x)
     cnt += drec[(size_t)si * nf + f].valid & drec[(size_t)sj * nf + f].valid;
   part[threadIdx.x] = cnt;
   __syncthreads();
@@ -92,13 +99,13 @@ __global__ void k_weights(const DelayRec* __restrict__ drec, int S, int nf,
     if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) wst[si * S + sj] += (double)part[0];
+  if (threadIdx.x == 0 && part[0] != 0) atomicAdd(&wst[si * S + sj], (double)part[0]);
 }
 
 hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* wst,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_weights, dim3(n_stations, n_stations), dim3(256), 0, s, drec, n_stations,
-                     nf, wst);
+  const dim3 grid(n_stations, n_stations, (nf + kWeightChunk - 1) / kWeightChunk);
+  hipLaunchKernelGGL(k_weights, grid, dim3(256), 0, s, drec, n_stations, nf, wst);
   return hipGetLastError();
 }
 
@@ -119,8 +126,21 @@ __global__ void k_finalise(const double2* __restrict__ vacc, int n_slots, size_t
   const int j = i + rem;
   const double w = wst[(i / P) * S + (j / P)];
   double2 a = vacc[e];
-  for (int q = 1; q < n_slots; ++q) {     // fixed slot order
-    const double2 b = vacc[e + q * slot_stride];
+  // fixed slot order; the loads of eight slots are issued together (a job of
+  // few channels and baselines can have over a hundred slots)
+  int q = 1;
+  for (; q + 8 <= n_slots; q += 8) {
+    double2 b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) b[u] = vacc[e + (size_t)(q + u) * slot_stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a.x += b[u].x;
+      a.y += b[u].y;
+    }
+  }
+  for (; q < n_slots; ++q) {
+    const double2 b = vacc[e + (size_t)q * slot_stride];
     a.x += b.x;
     a.y += b.y;
   }

@@ -21,8 +21,11 @@ namespace xc {
 constexpr int kSlots = 8;                 // pinned descriptor staging slots per context
 constexpr size_t kSlotBytes = 256 * 1024;
 constexpr size_t kAlign = 256;
-constexpr int kMaxBlockFrames = 2048;
+constexpr int kMaxBlockFrames = 65536;
+// Default frames per block: 2048, or more while the block's staged spectra
+// stay within kDefaultBlockBytes (small jobs run in fewer, larger rounds).
 constexpr int kDefaultBlockFrames = 2048;
+constexpr size_t kDefaultBlockBytes = (size_t)256 << 20;
 constexpr int kScaleFrames = 64;          // frames that set the MFMA path's channel scales
 constexpr int kF16TargetLog2 = 10;        // FP16: scaled RMS 2^10 (max 65504)
 constexpr int kF8TargetLog2 = 5;          // e4m3: scaled RMS 2^5 (max 448)

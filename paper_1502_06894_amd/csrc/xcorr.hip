@@ -55,9 +55,16 @@ xc_tuning effective_tuning(const xc_ctx* c, const xc_setup* s) {
 }
 
 static int block_frames(const xc_setup* s, const xc_tuning& tu) {
-  int64_t T = s->frames_per_block > 0 ? s->frames_per_block
-              : tu.frames_per_block > 0 ? tu.frames_per_block
-                                        : kDefaultBlockFrames;
+  int64_t T = s->frames_per_block > 0 ? s->frames_per_block : tu.frames_per_block;
+  if (T <= 0) {
+    const int eb = s->precision == XC_FP16_MFMA ? 4 : s->precision == XC_FP8_MFMA ? 2 : 8;
+    const size_t per_frame =
+        (size_t)s->n_subbands * s->n_stations * s->n_pols * s->n_chan * eb;
+    const size_t fit = per_frame > 0 ? kDefaultBlockBytes / per_frame : kDefaultBlockFrames;
+    T = fit > (size_t)kMaxBlockFrames ? kMaxBlockFrames
+        : fit > (size_t)kDefaultBlockFrames ? (int64_t)fit
+                                            : kDefaultBlockFrames;
+  }
   if (T > s->n_frames) T = s->n_frames;
   return (int)T;
 }

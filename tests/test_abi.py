@@ -110,10 +110,18 @@ def test_workspace_bytes_and_validation_on_host():
     s2, st2, keep2 = _setup(frames_per_block=32)   # two 32-frame block buffers < 100 frames
     assert lib.xc_workspace_bytes(None, C.byref(s2), st2) < n
     for bad in [dict(n_chan=300), dict(n_chan=64), dict(n_streams_recorded=3),
-                dict(n_pols=3), dict(n_stations=0), dict(n_frames=0), dict(frames_per_block=3000),
+                dict(n_pols=3), dict(n_stations=0), dict(n_frames=0), dict(frames_per_block=70000),
                 dict(precision=7)]:
         sb, stb, kb = _setup(**bad)
         assert lib.xc_workspace_bytes(None, C.byref(sb), stb) == 0, bad
+    # the default block of a small job: past 2048 frames while its spectra stay
+    # within 256 MiB (here the whole 10000-frame job in one block)
+    s4, st4, k4 = _setup(n_frames=10000)
+    s5, st5, k5 = _setup(n_frames=10000, frames_per_block=2048)
+    s6, st6, k6 = _setup(n_frames=10000, frames_per_block=10000)
+    n4 = lib.xc_workspace_bytes(None, C.byref(s4), st4)
+    assert n4 > lib.xc_workspace_bytes(None, C.byref(s5), st5)
+    assert n4 == lib.xc_workspace_bytes(None, C.byref(s6), st6)
     # sub-integration outside the polynomial span
     s3, st3, k3 = _setup(sub_start=200 * 32_000_000)
     assert lib.xc_workspace_bytes(None, C.byref(s3), st3) == 0
