@@ -143,6 +143,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   // at the store instead of held in registers.  Asks for 4 waves per SIMD.
   constexpr bool kLean = W == kFstageLean;
   static_assert(!kRamp || OUT == kOutF32, "the drift correction rewrites FP32 spectra");
+  static_assert(!kLean || 2 * E <= 32, "a lean input's codes fit one 32-bit register");
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
