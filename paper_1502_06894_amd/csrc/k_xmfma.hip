@@ -103,30 +103,40 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   }
 
   // stage loader: FB frames x M inputs x RW words, read along the channel words
-  // (coalesced) and stored row by row
-  constexpr int PER = (FB * 32 * RW + NT - 1) / NT;
-  uint32_t pre[PER];
+  // in 16-byte pieces (coalesced; a row starts 16-byte aligned) and stored word
+  // by word
+  constexpr int VEC = 4;
+  static_assert(RW % VEC == 0, "rows of whole 16-byte pieces");
+  constexpr int RV = RW / VEC;                       // pieces per row
+  constexpr int PER = (FB * 32 * RV + NT - 1) / NT;
+  uint4 pre[PER];
   auto gload = [&](int f0) {
     const int nfb = min(FB, nf - f0);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = threadIdx.x + i * NT;
-      const int w = q % RW, r = q / RW;            // r = fb * M + input
+      const int w = (q % RV) * VEC, r = q / RV;      // r = fb * M + input
       const int fb = r / M, mm = r - fb * M;
-      pre[i] = (r < FB * M && fb < nfb) ? src[((size_t)(f0 + fb) * M + mm) * row_words + w] : 0u;
+      pre[i] = (r < FB * M && fb < nfb)
+                   ? *reinterpret_cast<const uint4*>(src + ((size_t)(f0 + fb) * M + mm) * row_words + w)
+                   : make_uint4(0u, 0u, 0u, 0u);
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = threadIdx.x + i * NT;
-      const int w = q % RW, r = q / RW;
+      const int w = (q % RV) * VEC, r = q / RV;
       const int fb = r / M, mm = r - fb * M;
       if (r < FB * M) {
-        if constexpr (OUT == kOutF16)
-          lds[buf * STAGE + fb * FS + mm * RS + w] = pre[i];
-        else
-          lds[buf * STAGE + (w * 32 + mm) * FP + fb] = pre[i];
+        const uint32_t v4[VEC] = {pre[i].x, pre[i].y, pre[i].z, pre[i].w};
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+          if constexpr (OUT == kOutF16)
+            lds[buf * STAGE + fb * FS + mm * RS + w + u] = v4[u];
+          else
+            lds[buf * STAGE + ((w + u) * 32 + mm) * FP + fb] = v4[u];
+        }
       }
     }
   };
@@ -225,12 +235,18 @@ static hipError_t launch_cfg(const DevJob* job, int n_chan, int n_subbands, cons
                                     : (size_t)RW * 32 * (FB + 4)) * sizeof(uint32_t);
   const size_t scr = (size_t)NW * 32 * 33 * sizeof(float);
   if (scr > lds) lds = scr;
-  static bool attr_set = false;
-  if (!attr_set && lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_xmfma<OUT, KC, CPW, FB>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  static bool attr_set[64] = {};   // per device
+  if (lds > 65536) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    attr_set = true;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (!attr_set[dev]) {
+      e = hipFuncSetAttribute((const void*)k_xmfma<OUT, KC, CPW, FB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr_set[dev] = true;
+    }
   }
   dim3 grid(n_chan / KC, n_subbands);
   hipLaunchKernelGGL((k_xmfma<OUT, KC, CPW, FB>), grid, dim3(64 * NW), lds, s, job,
@@ -243,10 +259,14 @@ hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_sub
                         size_t slot_stride, int nf, hipStream_t s) {
   (void)slot_stride;
   if (M > 32 || n_chan < 32) return hipErrorInvalidValue;
+  // 16 channels per workgroup, 2 per wave; 32 (FP16) / 64 (e4m3) frames per LDS
+  // stage: 139 KB of LDS either way, one workgroup per CU (the accumulators take
+  // 96 registers per lane).  Measured on a C4 step against 16-frame stages:
+  // FP16 5.33 -> 5.07 ms, e4m3 4.42 -> 3.86 ms.
   if (out == kOutF16)
-    return launch_cfg<kOutF16, 16, 2, 16>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
+    return launch_cfg<kOutF16, 16, 2, 32>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
   if (out == kOutF8)
-    return launch_cfg<kOutF8, 16, 2, 16>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
+    return launch_cfg<kOutF8, 16, 2, 64>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
   return hipErrorInvalidValue;
 }
 
