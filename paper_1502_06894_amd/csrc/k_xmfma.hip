@@ -259,14 +259,15 @@ hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_sub
                         size_t slot_stride, int nf, hipStream_t s) {
   (void)slot_stride;
   if (M > 32 || n_chan < 32) return hipErrorInvalidValue;
-  // 16 channels per workgroup, 2 per wave; 32 (FP16) / 64 (e4m3) frames per LDS
-  // stage: 139 KB of LDS either way, one workgroup per CU (the accumulators take
-  // 96 registers per lane).  Measured on a C4 step against 16-frame stages:
-  // FP16 5.33 -> 5.07 ms, e4m3 4.42 -> 3.86 ms.
+  // 16 channels per workgroup, one per wave (16 waves, 110 registers: four
+  // waves per SIMD); 32 (FP16) / 64 (e4m3) frames per LDS stage, 139 KB of LDS,
+  // one workgroup per CU.  Measured on a C4 step: 16-frame stages -> these,
+  // FP16 5.33 -> 5.07 ms, e4m3 4.42 -> 3.86 ms; two channels per wave (8 waves)
+  // -> one, 5.07 -> 4.87 and 3.88 -> 3.70 ms.
   if (out == kOutF16)
-    return launch_cfg<kOutF16, 16, 2, 32>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
+    return launch_cfg<kOutF16, 16, 1, 32>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
   if (out == kOutF8)
-    return launch_cfg<kOutF8, 16, 2, 64>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
+    return launch_cfg<kOutF8, 16, 1, 64>(job, n_chan, n_subbands, spec, scale_exp, vacc, nf, s);
   return hipErrorInvalidValue;
 }
 
