@@ -279,6 +279,27 @@ def test_bad_frames_and_out_of_buffer(xc, corr):
     assert rel_l2(vis.cpu().numpy(), V) < TOL
 
 
+def test_invalid_frames_across_weight_chunks(xc, corr):
+    """One 5000-frame block (the default for a job this small), so the pair
+    weights are counted over three 2048-frame chunks; bad sync words and the
+    end of a recording fall in different chunks."""
+    job = configs.small_job(n_stations=3, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=5000,
+                            realistic=False, seed=11)
+    for s_, m in ((1, 10), (0, 45)):                   # FFT frames ~780 and ~3500
+        job.stations[s_].frames = job.stations[s_].frames.clone()
+        job.stations[s_].frames[m, 0] = 0
+    job.stations[2].frames = job.stations[2].frames[:-2].contiguous()   # the last frames
+    V, W = fx.correlate(job, threads=8)
+    assert W.min() < job.n_frames - 100
+    _on_gpu(xc, job)
+    vis, w = corr.correlate(job)
+    assert np.array_equal(w.cpu().numpy(), W.astype(np.float32))
+    assert rel_l2(vis.cpu().numpy(), V) < TOL
+    vis2, w2 = corr.correlate(job, frames_per_block=2048)
+    assert torch.equal(w, w2)
+    assert rel_l2(vis2.cpu().numpy(), V) < TOL
+
+
 def test_ingest_mask_and_supplied_mask(xc, corr):
     job = configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=200,
                             realistic=False, seed=8)
