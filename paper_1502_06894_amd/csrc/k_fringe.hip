@@ -5,6 +5,8 @@
 // column, the windowed peak and its parabolic refinement.
 #include <math.h>
 
+#include <atomic>
+
 #include "xc_fft.h"
 #include "xc_launch.h"
 #include "xc_runtime.h"
@@ -253,16 +255,16 @@ __global__ void __launch_bounds__(kFringeThreads)
 
 // One attribute call per kernel and device (LDS above 64 KB).
 template <class K>
-static hipError_t allow_lds(K kernel, size_t bytes, bool (&done)[64]) {
+static hipError_t allow_lds(K kernel, size_t bytes, std::atomic<bool> (&done)[64]) {
   if (bytes <= 65536) return hipSuccess;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  if (done[dev]) return hipSuccess;
+  if (done[dev].load()) return hipSuccess;
   e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)bytes);
-  if (e == hipSuccess) done[dev] = true;
+  if (e == hipSuccess) done[dev].store(true);
   return e;
 }
 
@@ -270,7 +272,7 @@ template <int D>
 static hipError_t launch_delay_d(const float2* vis, float2* F, const float2* tw, int n_sub,
                                  int n_sb, int nbl, int n_chan, hipStream_t s) {
   using Gm = RowGeom<D>;
-  static bool done[64] = {};
+  static std::atomic<bool> done[64];
   hipError_t e = allow_lds(k_fringe_delay<D>, Gm::lds_bytes, done);
   if (e != hipSuccess) return e;
   const long rows = (long)n_sub * n_sb * nbl;
@@ -283,7 +285,7 @@ static hipError_t launch_delay_d(const float2* vis, float2* F, const float2* tw,
 template <int R>
 static hipError_t launch_rate_r(const xc_fringe_setup* fs, const float2* F, const float2* tw,
                                 xc_fringe_peak* peaks, float2* map, hipStream_t s) {
-  static bool done[64] = {};
+  static std::atomic<bool> done[64];
   hipError_t e = allow_lds(k_fringe_rate<R>, RateGeom<R>::lds_bytes, done);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fringe_rate<R>, dim3(fs->n_subbands * fs->n_baselines),

@@ -4,6 +4,8 @@
 // threads); each group loads the payload words of its window once and reuses
 // them for every input (subband, pol) of the station, since all recorded
 // streams of a time sample share a word.
+#include <atomic>
+
 #include "xc_fft.h"
 #include "xc_launch.h"
 
@@ -391,13 +393,15 @@ static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* d
                             const PhaseRec* prec, const float2* tw, void* spec,
                             const int8_t* scale_exp, int nf, unsigned* ctr, hipStream_t s) {
   using Gm = FGeom<N, fstage_twm<N, W>()>;
-  // per device: LDS attribute set, and how many workgroups fill the GPU
-  static int resident[64] = {};
+  // per device: LDS attribute set, and how many workgroups fill the GPU (set
+  // once; callers on several host threads may race to set the same value)
+  static std::atomic<int> resident[64];
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  if (!resident[dev]) {
+  int res = resident[dev].load();
+  if (!res) {
     e = hipFuncSetAttribute((const void*)k_fstage<N, W, OUT>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::lds_bytes);
     int per_cu = 0, n_cu = 0;
@@ -406,10 +410,11 @@ static hipError_t launch_nw(const DevJob* job, int n_stations, const DelayRec* d
                                                        Gm::lds_bytes);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    resident[dev] = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+    res = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+    resident[dev].store(res);
   }
   const long tasks = (long)((nf + Gm::G - 1) / Gm::G) * n_stations;
-  const int grid = (int)(tasks < resident[dev] ? tasks : resident[dev]);
+  const int grid = (int)(tasks < res ? tasks : res);
   hipLaunchKernelGGL((k_fstage<N, W, OUT>), dim3(grid), dim3(Gm::WG), Gm::lds_bytes, s, job, drec,
                      prec, tw, spec, scale_exp, nf, ctr);
   return hipGetLastError();

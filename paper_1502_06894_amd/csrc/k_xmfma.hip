@@ -16,6 +16,8 @@
 // reads (measured faster there).  After the block, G21 is transposed through
 // LDS, every element is unscaled by 2^-(e_i + e_j) and added to the FP64
 // accumulator slot of the FP32 path.
+#include <atomic>
+
 #include "xc_launch.h"
 
 namespace xc {
@@ -235,17 +237,17 @@ static hipError_t launch_cfg(const DevJob* job, int n_chan, int n_subbands, cons
                                     : (size_t)RW * 32 * (FB + 4)) * sizeof(uint32_t);
   const size_t scr = (size_t)NW * 32 * 33 * sizeof(float);
   if (scr > lds) lds = scr;
-  static bool attr_set[64] = {};   // per device
+  static std::atomic<bool> attr_set[64];   // per device
   if (lds > 65536) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    if (!attr_set[dev]) {
+    if (!attr_set[dev].load()) {
       e = hipFuncSetAttribute((const void*)k_xmfma<OUT, KC, CPW, FB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
-      attr_set[dev] = true;
+      attr_set[dev].store(true);
     }
   }
   dim3 grid(n_chan / KC, n_subbands);
