@@ -183,7 +183,8 @@ int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
  * the FP32 path's tolerance). */
 typedef struct {
   int32_t fstage_waves_per_simd;   /* F-stage variant: 0 = default (7 for FFT lengths of
-                                      8192 and more, else 1); 1 = one task per station and
+                                      8192 and more; 8 for dual-pol FP32 jobs with FFT
+                                      lengths up to 2048; else 1); 1 = one task per station and
                                       frame group, the next task's window words loaded
                                       during the transforms; 2 = the pols of a subband
                                       share their fringe phasors (fewer operations, more
@@ -196,8 +197,11 @@ typedef struct {
                                       group of up to four inputs, whose 2-bit codes are
                                       packed into one register per input before the
                                       transforms (split twiddles, 4 waves per SIMD; the
-                                      window words are loaded once per group).  2-4
-                                      apply to FP32 spectra only. */
+                                      window words are loaded once per group); 8 = as
+                                      1, with the pols of a subband sharing their fringe
+                                      phasors, no word prefetch and the fractional-delay
+                                      phasors stepped at the store (bit-identical to 1).
+                                      2-4 and 8 apply to FP32 spectra only. */
   int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
                                       stages filled by direct memory-to-LDS loads (64-channel
                                       tiles, at most 32 inputs per subband; the default where

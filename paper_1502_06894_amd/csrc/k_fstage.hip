@@ -131,7 +131,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   constexpr int kAnchor = E / 2 < 8 ? E / 2 : 8;   // exact phasor every kAnchor samples
   // W = 2: a subband's pols share one set of fringe phasors (both see the same
   // fringe phase), held in registers from the first pol to the second
-  constexpr bool kShare = W == 2;
+  constexpr bool kShare = W == 2 || W == kFstageShare;
   // W = kFstageRatePass: the drift-correction pass over the stations that ask
   // for it: the window is weighted by the ramp (n - N/2) before the transform,
   // and the stored spectrum Y (from the regular pass) becomes
@@ -233,7 +233,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
 
   // The next task's words are loaded while this task is transformed, except
   // for N = 16384 (1024 threads, 128 registers each: no room for them).
-  constexpr bool kPrefetch = N <= 8192 && !kLean;
+  constexpr bool kPrefetch = N <= 8192 && !kLean && W != kFstageShare;
   while (task < n_tasks) {
     if (threadIdx.x == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
     __syncthreads();
@@ -251,7 +251,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     // fractional-delay phasors of this thread's kept output bins
     // k = t + b T + r N/16 (b < BL, r < 8): exp(2 pi i k d / N) =
     // exp(2 pi i (t + b T) d / N) * exp(2 pi i d / 16)^r
-    constexpr int FDK = kLean ? 1 : 8;
+    constexpr bool kFdStep = kLean || W == kFstageShare;
+    constexpr int FDK = kFdStep ? 1 : 8;
     float2 fd[BL][FDK];
     float2 fd_st;
     {
@@ -351,7 +352,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
 #pragma unroll
           for (int rr = 0; rr < 8; ++rr) {
             const int k = t + b * T + rr * (N / 16);
-            if constexpr (kLean) {
+            if constexpr (kFdStep) {
               if (rr > 0) fdr = cmul(fdr, fd_st);
             } else {
               fdr = fd[b][rr];
@@ -463,6 +464,9 @@ static hipError_t launch_n(const DevJob* job, int n_stations, int n_inputs, cons
       return launch_nw<N, 4, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
     case 5:
       return launch_nw<N, 5, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr, nf, ctr, s);
+    case kFstageShare:
+      return launch_nw<N, kFstageShare, kOutF32>(job, n_stations, drec, prec, tw, spec, nullptr,
+                                                 nf, ctr, s);
     case kFstageLean:
       return launch_nw<N, kFstageLean, kOutF32>(job, lean_units(n_stations, n_inputs), drec, prec,
                                                 tw, spec, nullptr, nf, ctr, s);

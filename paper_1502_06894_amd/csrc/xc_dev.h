@@ -196,8 +196,11 @@ __device__ inline float2 phasor_turns(float x) {
 // x - floor(x) of a double, as float (in [0, 1]).
 __device__ inline float frac_f(double x) { return (float)(x - floor(x)); }
 
+// Complex product with its two fused multiply-adds written out, so that every
+// kernel variant rounds it the same way (left to the compiler, the fusion
+// depends on the surrounding code).
 __device__ inline float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 
 }  // namespace xc

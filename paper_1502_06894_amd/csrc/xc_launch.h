@@ -27,8 +27,9 @@ constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, satura
 inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
 
 // waves: F-stage variant (0 = default: kFstageLean for N >= kLeanMinN, else one task per
-// station and frame group; 1 = the latter at every N; 2..5, 7 as the tuning field describes;
-// FP32 output only except 5 and 7).  kFstageLean: tasks of up to four inputs whose 2-bit
+// station and frame group; 1 = the latter at every N; 2..5, 7, 8 as the tuning field
+// describes; FP32 output only except 5 and 7).  The caller picks kFstageShare for dual-pol
+// FP32 jobs (fstage_variant()).  kFstageLean: tasks of up to four inputs whose 2-bit
 // codes are packed into one register each, so the window words are not held across the
 // transforms (fewer registers, more resident waves, for reloading the words per group).
 // kFstageRatePass: the drift-correction pass, run after the regular F stage on
@@ -37,8 +38,20 @@ inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 
 // takes the next task counter, ctr + 1 of the regular pass).
 constexpr int kFstageRatePass = 6;
 constexpr int kFstageLean = 7;
+// kFstageShare: the pols of a subband share their fringe phasors (held from the
+// first pol to the second), with no word prefetch and the fractional-delay
+// phasors stepped at the store to make room for them; the default for dual-pol
+// FP32 jobs up to kShareMaxN (measured on MI355X: a C2-shaped F stage 3.5 %
+// faster; at N = 4096 the registers would cost a wave per SIMD).
+constexpr int kFstageShare = 8;
+constexpr int kShareMaxN = 2048;
 constexpr int kLeanMinN = 8192;
 constexpr int kLeanGroup = 4;   // inputs per lean task
+// The F-stage variant a job runs: the tuned one, else kFstageShare where it pays.
+inline int fstage_variant(int tuned, int n_pols, int n_chan, int out) {
+  if (tuned != 0) return tuned;
+  return n_pols == 2 && 2 * n_chan <= kShareMaxN && out == kOutF32 ? kFstageShare : 0;
+}
 constexpr int kMaxRateCorrectN = 16384;   // the drift correction runs in the one-workgroup FFT
 // ctr: task counter, zero at launch (launch_delays clears it), one per concurrent launch.
 // scratch: fstage_scratch_bytes(...) of device memory (N = 32768 only; else unused).

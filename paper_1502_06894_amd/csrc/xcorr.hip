@@ -311,7 +311,8 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
     if (e != hipSuccess) return hip_fail(c, e, "delays");
     e = timed(c, XC_K_FSTAGE, stream, [&] {
       return launch_fstage(N, dj, S, nsb * s->n_pols, drec_p, prec_p, c->d_tw, spec_p, sexp, nf,
-                           tu.fstage_waves_per_simd, L.out, ctr_p,
+                           fstage_variant(tu.fstage_waves_per_simd, s->n_pols, s->n_chan, L.out),
+                           L.out, ctr_p,
                            reinterpret_cast<float2*>(arena + L.scratch), stream);
     });
     if (e != hipSuccess) return hip_fail(c, e, "fstage");
@@ -555,7 +556,8 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
 int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
   if (!c || !t) return XC_E_INVAL;
   const bool ok = t->fstage_waves_per_simd >= 0 &&
-                  (t->fstage_waves_per_simd <= 5 || t->fstage_waves_per_simd == kFstageLean) &&
+                  (t->fstage_waves_per_simd <= 5 || t->fstage_waves_per_simd == kFstageShare ||
+                   t->fstage_waves_per_simd == kFstageLean) &&
                   (t->xmac_frames_per_stage == 0 || t->xmac_frames_per_stage == 1 ||
                    t->xmac_frames_per_stage == 2 || t->xmac_frames_per_stage == 4 ||
                    t->xmac_frames_per_stage == 8) &&
@@ -693,7 +695,9 @@ int xc_debug_spectra(xc_ctx* c, const xc_setup* s, const xc_station* st, int64_t
   hipError_t e = launch_delays(dj, s->n_stations, s->n_subbands, frame0, n, drec, prec, ctr, stream);
   if (e == hipSuccess)
     e = launch_fstage(2 * s->n_chan, dj, s->n_stations, s->n_subbands * s->n_pols, drec, prec,
-                      c->d_tw, spectra, nullptr, n, p.tu.fstage_waves_per_simd, kOutF32, ctr,
+                      c->d_tw, spectra, nullptr, n,
+                      fstage_variant(p.tu.fstage_waves_per_simd, s->n_pols, s->n_chan, kOutF32),
+                      kOutF32, ctr,
                       reinterpret_cast<float2*>(p.arena + p.L.scratch), stream);
   if (e == hipSuccess && any_rate_correct(s, st))
     e = launch_fstage(2 * s->n_chan, dj, s->n_stations, s->n_subbands * s->n_pols, drec, prec,
