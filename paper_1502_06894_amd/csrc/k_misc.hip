@@ -33,14 +33,15 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// One thread per (station, block frame).  Writes the integer/fractional delay
-// and validity, and the fringe phase terms of every subband.
+// One thread per (station, block frame, subband).  Writes the subband's fringe
+// phase terms; the subband-0 thread also the integer/fractional delay, the
+// validity and the delay rate of the frame.
 __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
                          DelayRec* __restrict__ drec, PhaseRec* __restrict__ prec,
                          unsigned* __restrict__ ctr) {
   const int fl = blockIdx.x * blockDim.x + threadIdx.x;
-  const int s = blockIdx.y;
-  if (ctr && fl == 0 && s == 0) {
+  const int s = blockIdx.y, sb = blockIdx.z;
+  if (ctr && fl == 0 && s == 0 && sb == 0) {
     ctr[0] = 0u;   // the F stage's task counter
     ctr[1] = 0u;   // the drift-correction pass's
   }
@@ -48,6 +49,12 @@ __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
   const DevJob& J = *job;
   const DevStation& S = J.st[s];
   const int64_t f = f0 + fl;
+  const int64_t num = J.sub_start + f * (int64_t)J.N + (int64_t)(J.N / 2);
+  const double t = (double)num / J.fs;
+  // one thread per (frame, station, subband): each writes its subband's phase
+  // record, the subband-0 thread also the frame's delay record
+  prec[((size_t)s * J.n_subbands + sb) * nf + fl] = frame_phase(S, J, sb, t);
+  if (sb != 0) return;
   DelayRec r;
   frame_delay(S, J, f, &r.n_int, &r.d);
   r.base = J.sub_start + f * (int64_t)J.N + r.n_int - S.first_sample;
@@ -58,21 +65,16 @@ __global__ void k_delays(const DevJob* __restrict__ job, int64_t f0, int nf,
     for (int64_t m = a; m <= b; ++m) ok = ok && S.frame_ok[m] != 0;
   }
   r.valid = ok ? 1 : 0;
-  const int64_t num = J.sub_start + f * (int64_t)J.N + (int64_t)(J.N / 2);
-  const double t = (double)num / J.fs;
   double d1, d2;
   poly_derivs(S.delay_poly, S.poly_deg, t, d1, d2);
   r.rate = (float)d1;
   drec[(size_t)s * nf + fl] = r;
-  for (int sb = 0; sb < J.n_subbands; ++sb)
-    prec[((size_t)s * J.n_subbands + sb) * nf + fl] = frame_phase(S, J, sb, t);
 }
 
 hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
                          DelayRec* drec, PhaseRec* prec, unsigned* ctr, hipStream_t s) {
-  (void)n_subbands;
   const int b = 64;
-  dim3 grid((nf + b - 1) / b, n_stations);
+  dim3 grid((nf + b - 1) / b, n_stations, n_subbands);
   hipLaunchKernelGGL(k_delays, grid, dim3(b), 0, s, job, f0, nf, drec, prec, ctr);
   return hipGetLastError();
 }
