@@ -41,7 +41,7 @@ constexpr int kFstageLean = 7;
 // kFstageShare: the pols of a subband share their fringe phasors (held from the
 // first pol to the second), with no word prefetch and the fractional-delay
 // phasors stepped at the store to make room for them; the default for dual-pol
-// FP32 jobs up to kShareMaxN (measured on MI355X: a C2-shaped F stage 3.5 %
+// FP32 jobs up to kShareMaxN (measured on MI355X: a C2-shaped F stage 3.3 %
 // faster; at N = 4096 the registers would cost a wave per SIMD).
 constexpr int kFstageShare = 8;
 constexpr int kShareMaxN = 2048;
