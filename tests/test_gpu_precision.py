@@ -59,7 +59,8 @@ def _c4_shaped():
     dict(n_stations=32, n_subbands=2, n_pols=1, n_chan=512, C=4, n_frames=96, realistic=False),
     dict(n_stations=6, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=75),
     None,
-], ids=["m32", "dualpol", "c4shape"])
+    dict(n_stations=4, n_subbands=5, n_pols=1, n_chan=4096, C=8, n_frames=24, realistic=False),
+], ids=["m32", "dualpol", "c4shape", "lean_5in"])
 def test_mfma_precision_bound(xc, corr, prec, kw):
     job = _c4_shaped() if kw is None else configs.small_job(**kw, seed=17)
     V, W = fx.correlate(job, threads=8)
