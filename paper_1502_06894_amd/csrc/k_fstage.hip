@@ -594,8 +594,197 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf) {
-  return N == kBigN ? (size_t)n_stations * nf * n_inputs * kBigN * sizeof(float2) : 0;
+// ---------------------------------------------------------------- N = 32768, two folded halves
+// The kept half of a 32768-point frame (channels < 16384) without scratch
+// memory, as two 16384-point transforms.  With W = exp(-2 pi i / 32768),
+//   X[2k + h] = sum_{n < 16384} (y_h[n] + y_h[n + 16384]) exp(-2 pi i k n / 16384),
+//   y_h[n] = x[n] W^(h n),
+// and x[n] W^(h n) is the sample rotated by the fringe phase less h n / 32768
+// turns: pass h (0, 1) rotates with phi0 - h / 2 and phi1 - h / 32768 (about the
+// frame centre), folds the frame's two halves and transforms them in the
+// one-workgroup FFT of N = 16384, whose kept bins k < 8192 are channels 2k + h.
+// Tasks are (station, frame, group of up to kLeanGroup inputs), the group's
+// codes packed as in the lean F stage (two registers per input).  FP32 spectra.
+constexpr int kHalfN = kBigN / 2;
+
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T)))
+    k_fhalf(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
+            const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
+            float2* __restrict__ spec, int nf, unsigned* __restrict__ ctr) {
+  using Gm = FGeom<kHalfN, kTwSplit>;
+  constexpr int T = Gm::T, E = Gm::E;
+  static_assert(Gm::G == 1 && 2 * E <= 32, "one frame per workgroup, codes in 32 bits");
+  __shared__ int next_task;
+  extern __shared__ float2 lds_all[];
+  const DevJob& J = *job;
+  const int t = threadIdx.x;
+  const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
+  const int n_ig = (J.n_inputs + kLeanGroup - 1) / kLeanGroup;
+  const int per_station = nf * n_ig;
+  const int n_tasks = per_station * J.n_stations;
+  unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds_all);
+  float* lut = reinterpret_cast<float*>(lds_b + Gm::lut_off);
+  if (t < 8) {
+    const float lv[4] = {-3.3359f, -1.0f, 1.0f, 3.3359f};
+    lut[t] = t < 4 ? lv[t] : 0.0f;
+  }
+  float2* tw_tab = reinterpret_cast<float2*>(lds_b + Gm::tw_off);
+  tw_split_fill<kHalfN>(tw_tab, tw, t, blockDim.x);
+  __syncthreads();
+  constexpr double TD = (double)T;
+
+  int task = blockIdx.x;
+  while (task < n_tasks) {
+    const int s = task / per_station;
+    const int rem = task - s * per_station;
+    const int fl = __builtin_amdgcn_readfirstlane(rem / n_ig);
+    const int in_lo = (rem - fl * n_ig) * kLeanGroup;
+    const int in_hi = min(in_lo + kLeanGroup, J.n_inputs);
+    const DelayRec r = drec[(size_t)s * nf + fl];
+    const bool valid = r.valid != 0;
+    const float* lut_t = lut + (valid ? 0 : 4);
+    // the group's codes of samples t + e T (lo) and 16384 + t + e T (hi)
+    uint32_t c_lo[kLeanGroup], c_hi[kLeanGroup];
+    {
+      // one half of the window at a time (16 words in flight)
+      FrameCursor c;
+      int sh0 = 0;
+      if (valid) {
+        c = make_cursor(J, r.base);
+        sh0 = sample_shift(J, c, t);   // 16384 is a whole number of words
+      }
+      auto pack = [&](int off, uint32_t (&dst)[kLeanGroup]) {
+        uint32_t w[E];
+        if (valid) {
+          const uint32_t* words = J.st[s].words;
+#pragma unroll
+          for (int e = 0; e < E; ++e) w[e] = *sample_word(J, words, c, off + t + e * T);
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) w[e] = 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kLeanGroup; ++i) {
+          const int sh = sh0 + 2 * J.stream_map[min(in_lo + i, in_hi - 1)];
+          uint32_t a = 0;
+#pragma unroll
+          for (int e = 0; e < E; ++e) a |= ((w[e] >> sh) & 3u) << (2 * e);
+          dst[i] = a;
+        }
+      };
+      pack(0, c_lo);
+      pack(kHalfN, c_hi);
+    }
+    const float dd = (float)r.d;
+    const float2 fd_st = phasor_turns(dd * (1.0f / 16.0f));   // 2048 channels on
+#pragma unroll 1
+    for (int in = in_lo; in < in_hi; ++in) {
+      const int sb = in / P, p = in - sb * P;
+      const int i = in - in_lo;
+      uint32_t cl = c_lo[0], ch = c_hi[0];
+#pragma unroll
+      for (int j = 1; j < kLeanGroup; ++j) {
+        cl = i == j ? c_lo[j] : cl;
+        ch = i == j ? c_hi[j] : ch;
+      }
+      const PhaseRec ph = prec[((size_t)s * n_sb + sb) * nf + fl];
+      float2* row = spec + ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        const double phi0 = ph.phi0 - 0.5 * h, phi1 = ph.phi1 - (double)h / (double)kBigN;
+        const double phi2 = ph.phi2;
+        // centred index of sample n is n - 16384: t - 16384 + e T (lo), t + e T (hi);
+        // exact phasors every 8 samples where the quadratic term matters, else once
+        const bool quad = fabs(phi2) * TD * TD * (double)(E * (E - 1)) > 1e-8;
+        float2 v[E];
+        auto anchor = [&](double nc, float2& z, float2& w) {
+          z = phasor_turns(frac_f(fma(fma(phi2, nc, phi1), nc, phi0)));
+          w = phasor_turns(frac_f(phi1 * TD + phi2 * TD * (2.0 * nc + TD)));
+        };
+        auto sample = [&](int e, float2 zl, float2 zh) {
+          const float ql = lut_t[(cl >> (2 * e)) & 3u], qh = lut_t[(ch >> (2 * e)) & 3u];
+          v[e] = make_float2(fmaf(ql, zl.x, qh * zh.x), fmaf(ql, zl.y, qh * zh.y));
+        };
+        float2 zl, wl, zh, wh;
+        if (quad) {
+          const float2 rho = phasor_turns(frac_f(2.0 * phi2 * TD * TD));
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (e % 8 == 0) {
+              anchor((double)(t - kHalfN) + (double)e * TD, zl, wl);
+              anchor((double)t + (double)e * TD, zh, wh);
+            } else {
+              zl = cmul(zl, wl);
+              zh = cmul(zh, wh);
+              wl = cmul(wl, rho);
+              wh = cmul(wh, rho);
+            }
+            sample(e, zl, zh);
+          }
+        } else {
+          anchor((double)(t - kHalfN), zl, wl);
+          anchor((double)t, zh, wh);
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (e > 0) {
+              zl = cmul(zl, wl);
+              zh = cmul(zh, wh);
+            }
+            sample(e, zl, zh);
+          }
+        }
+        fft_forward<kHalfN>(v, lds_all, TwSplit<kHalfN>{tw_tab}, t);
+        // v[q] = bin t + q T of the folded transform; the kept bins (q < 8) are
+        // channels 2 (t + q T) + h, whose fractional-delay phasor is
+        // exp(2 pi i (2 (t + q T) + h) d / 32768)
+        float2 fdr = phasor_turns((float)(2 * t + h) * dd * (1.0f / (float)kBigN));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          if (q > 0) fdr = cmul(fdr, fd_st);
+          const float2 y = valid ? cmul(v[q], fdr) : make_float2(0.f, 0.f);
+          put_spec<kOutF32, false>(row, (size_t)(2 * (t + q * T) + h), y, 0);
+        }
+        __syncthreads();   // the next pass reuses lds
+      }
+    }
+    if (t == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
+    __syncthreads();
+    task = next_task;
+  }
+}
+
+static hipError_t launch_half(const DevJob* job, int n_stations, int n_inputs,
+                              const DelayRec* drec, const PhaseRec* prec, const float2* tw,
+                              float2* spec, int nf, unsigned* ctr, hipStream_t s) {
+  using Gm = FGeom<kHalfN, kTwSplit>;
+  static std::atomic<int> resident[64];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  int res = resident[dev].load();
+  if (!res) {
+    e = hipFuncSetAttribute((const void*)k_fhalf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)Gm::lds_bytes);
+    int per_cu = 0, n_cu = 0;
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fhalf, Gm::WG, Gm::lds_bytes);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    res = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+    resident[dev].store(res);
+  }
+  const long tasks = (long)nf * lean_units(n_stations, n_inputs);
+  const int grid = (int)(tasks < res ? tasks : res);
+  hipLaunchKernelGGL(k_fhalf, dim3(grid), dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec, tw,
+                     spec, nf, ctr);
+  return hipGetLastError();
+}
+
+size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf, int out) {
+  // the four-step path's rows (the FP32 path folds its halves instead)
+  return N == kBigN && out != kOutF32 ? (size_t)n_stations * nf * n_inputs * kBigN * sizeof(float2)
+                                      : 0;
 }
 
 static hipError_t launch_big(const DevJob* job, int n_stations, int n_inputs,
@@ -637,9 +826,15 @@ hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,
                          const DelayRec* drec, const PhaseRec* prec, const float2* tw,
                          void* spec, const int8_t* scale_exp, int nf, int waves, int out,
                          unsigned* ctr, float2* scratch, hipStream_t s) {
-  if (N == kBigN)
+  if (N == kBigN) {
+    if (out == kOutF32) {
+      if (!ctr) return hipErrorInvalidValue;
+      return launch_half(job, n_stations, n_inputs, drec, prec, tw, static_cast<float2*>(spec),
+                         nf, ctr, s);
+    }
     return launch_big(job, n_stations, n_inputs, drec, prec, tw, spec, scale_exp, nf, out,
                       scratch, s);
+  }
   if (!ctr) return hipErrorInvalidValue;
   switch (N) {
 #define XC_FCASE(NN)                                                                      \

@@ -54,14 +54,15 @@ inline int fstage_variant(int tuned, int n_pols, int n_chan, int out) {
 }
 constexpr int kMaxRateCorrectN = 16384;   // the drift correction runs in the one-workgroup FFT
 // ctr: task counter, zero at launch (launch_delays clears it), one per concurrent launch.
-// scratch: fstage_scratch_bytes(...) of device memory (N = 32768 only; else unused).
+// scratch: fstage_scratch_bytes(...) of device memory (N = 32768 with FP16 / e4m3 spectra
+// only; else unused).
 hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,
                          const DelayRec* drec, const PhaseRec* prec, const float2* tw,
                          void* spec, const int8_t* scale_exp, int nf, int waves, int out,
                          unsigned* ctr, float2* scratch, hipStream_t s);
 // Scratch the F stage needs for nf frames (nonzero for N = 32768: its four-step
 // FFT goes through memory).
-size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf);
+size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf, int out);
 // Power-of-two exponents per (subband, input, channel) that bring the mean
 // |Y|^2 of the first nf frames (FP32 spectra [n_sb][nf][M][n_chan]) to
 // target_log2 (i.e. RMS 2^target_log2); 0 when a channel has no power.

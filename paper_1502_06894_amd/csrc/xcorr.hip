@@ -170,7 +170,7 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, b
   L.sexp = off;
   if (L.out != kOutF32) off += align_up((size_t)nsb * M * s->n_chan);
   L.scratch = off;
-  off += align_up(fstage_scratch_bytes(2 * s->n_chan, S, nsb * s->n_pols, L.T));
+  off += align_up(fstage_scratch_bytes(2 * s->n_chan, S, nsb * s->n_pols, L.T, L.out));
   L.fps = xmac_frames_per_split(L.T, M, s->n_chan, nsb);
   L.n_slots = L.out == kOutF32 ? (L.T + L.fps - 1) / L.fps : 1;
   L.slot_stride = (size_t)nsb * nbl * s->n_chan;
