@@ -603,9 +603,10 @@ __global__ void __launch_bounds__(256)
 // turns: pass h (0, 1) rotates with phi0 - h / 2 and phi1 - h / 32768 (about the
 // frame centre), folds the frame's two halves and transforms them in the
 // one-workgroup FFT of N = 16384, whose kept bins k < 8192 are channels 2k + h.
-// Tasks are (station, frame, group of up to kLeanGroup inputs), the group's
+// Tasks are (station, frame, group of up to kHalfGroup inputs), the group's
 // codes packed as in the lean F stage (two registers per input).  FP32 spectra.
 constexpr int kHalfN = kBigN / 2;
+constexpr int kHalfGroup = kLeanGroup;   // inputs per task (2 or 1: hardly fewer spills)
 
 __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T)))
     k_fhalf(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
@@ -619,7 +620,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
   const DevJob& J = *job;
   const int t = threadIdx.x;
   const int P = J.n_pols, M = J.M, n_chan = J.n_chan, n_sb = J.n_subbands;
-  const int n_ig = (J.n_inputs + kLeanGroup - 1) / kLeanGroup;
+  const int n_ig = (J.n_inputs + kHalfGroup - 1) / kHalfGroup;
   const int per_station = nf * n_ig;
   const int n_tasks = per_station * J.n_stations;
   unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds_all);
@@ -638,13 +639,13 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
     const int s = task / per_station;
     const int rem = task - s * per_station;
     const int fl = __builtin_amdgcn_readfirstlane(rem / n_ig);
-    const int in_lo = (rem - fl * n_ig) * kLeanGroup;
-    const int in_hi = min(in_lo + kLeanGroup, J.n_inputs);
+    const int in_lo = (rem - fl * n_ig) * kHalfGroup;
+    const int in_hi = min(in_lo + kHalfGroup, J.n_inputs);
     const DelayRec r = drec[(size_t)s * nf + fl];
     const bool valid = r.valid != 0;
     const float* lut_t = lut + (valid ? 0 : 4);
     // the group's codes of samples t + e T (lo) and 16384 + t + e T (hi)
-    uint32_t c_lo[kLeanGroup], c_hi[kLeanGroup];
+    uint32_t c_lo[kHalfGroup], c_hi[kHalfGroup];
     {
       // one half of the window at a time (16 words in flight)
       FrameCursor c;
@@ -653,7 +654,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
         c = make_cursor(J, r.base);
         sh0 = sample_shift(J, c, t);   // 16384 is a whole number of words
       }
-      auto pack = [&](int off, uint32_t (&dst)[kLeanGroup]) {
+      auto pack = [&](int off, uint32_t (&dst)[kHalfGroup]) {
         uint32_t w[E];
         if (valid) {
           const uint32_t* words = J.st[s].words;
@@ -664,7 +665,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
           for (int e = 0; e < E; ++e) w[e] = 0u;
         }
 #pragma unroll
-        for (int i = 0; i < kLeanGroup; ++i) {
+        for (int i = 0; i < kHalfGroup; ++i) {
           const int sh = sh0 + 2 * J.stream_map[min(in_lo + i, in_hi - 1)];
           uint32_t a = 0;
 #pragma unroll
@@ -683,7 +684,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
       const int i = in - in_lo;
       uint32_t cl = c_lo[0], ch = c_hi[0];
 #pragma unroll
-      for (int j = 1; j < kLeanGroup; ++j) {
+      for (int j = 1; j < kHalfGroup; ++j) {
         cl = i == j ? c_lo[j] : cl;
         ch = i == j ? c_hi[j] : ch;
       }
@@ -774,7 +775,7 @@ static hipError_t launch_half(const DevJob* job, int n_stations, int n_inputs,
     res = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
     resident[dev].store(res);
   }
-  const long tasks = (long)nf * lean_units(n_stations, n_inputs);
+  const long tasks = (long)nf * n_stations * ((n_inputs + kHalfGroup - 1) / kHalfGroup);
   const int grid = (int)(tasks < res ? tasks : res);
   hipLaunchKernelGGL(k_fhalf, dim3(grid), dim3(Gm::WG), Gm::lds_bytes, s, job, drec, prec, tw,
                      spec, nf, ctr);
