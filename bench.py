@@ -32,10 +32,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-# FP32 vector FMA without packed-FP32 instructions (this build disables them):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz (the published 157.3 counts packed FP32)
-FP32_VECTOR_PEAK_TFS = 78.6
-FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published
+FP32_PEAK_TFLOPS = 157.3       # MI355X vector FP32, published (counts packed FP32 FMA)
+# The issue ceiling of this build's FP32 code: packed-FP32 instructions are
+# disabled, so one FMA per lane per cycle: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops x 2.4 GHz.  Reported beside the published peak, never in its place.
+FP32_ISSUE_CEILING_TFS = 78.6
 
 
 def log(msg: str):
@@ -70,8 +71,10 @@ def make_job(name: str, frames: int = 0):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile(kind: str, src_hash: str, launches_units: float):
-    """HBM bytes per launch from committed counter summaries, if they match the kernel."""
+def traffic_from_profile(kind: str, src_hash: str):
+    """HBM bytes per station-sample of a kernel kind, from the counter summary
+    profiles/hbm_counters.json (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+    copy's counts), or None when it is missing or was taken on other sources."""
     path = os.path.join(ROOT, "profiles", "hbm_counters.json")
     if not os.path.exists(path):
         return None
@@ -80,7 +83,46 @@ def traffic_from_profile(kind: str, src_hash: str, launches_units: float):
     e = d.get(kind)
     if not e or e.get("source_hash") != src_hash:
         return None
-    return e.get("bytes_per_launch")
+    return e.get("bytes_per_station_sample")
+
+
+def roofline(kind: str, bytes_per_ss: float, flops_per_ss: float, src_files, prof_entry,
+             ss_total: float) -> dict:
+    """Roofline record of one kernel kind from its live HIP-event time.
+
+    T_bound = max(bytes / 8 TB/s, flops / 157.3 TFLOP/s) per launch (published
+    MI355X peaks); the roof with the larger time binds; frac = T_bound / T_meas.
+    `traffic` is the HBM bytes per launch measured by the FETCH_SIZE and
+    WRITE_SIZE counters (committed summary, same kernel sources) or null."""
+    ms_tot, n_launch = prof_entry
+    t_meas = ms_tot * 1e-3 / n_launch
+    ss_launch = ss_total / n_launch
+    alg_bytes = bytes_per_ss * ss_launch
+    alg_flops = flops_per_ss * ss_launch
+    t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = alg_flops / (FP32_PEAK_TFLOPS * 1e12)
+    src_hash = kernel_source_hash(src_files)
+    tr = traffic_from_profile(kind, src_hash)
+    hbm = {"achieved": round(alg_bytes / t_meas / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(t_hbm / t_meas, 4)}
+    alu = {"achieved": round(alg_flops / t_meas / 1e12, 2), "peak": FP32_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(t_alu / t_meas, 4),
+           "issue_ceiling_nonpacked_tflops": FP32_ISSUE_CEILING_TFS,
+           "frac_of_issue_ceiling": round(alg_flops / t_meas / 1e12 / FP32_ISSUE_CEILING_TFS, 4)}
+    bound = "hbm" if t_hbm >= t_alu else "alu"
+    main, side = (hbm, alu) if bound == "hbm" else (alu, hbm)
+    return {"bound": bound, "achieved": main["achieved"], "peak": main["peak"],
+            "unit": main["unit"], "frac": main["frac"],
+            "traffic": None if tr is None else round(tr * ss_launch),
+            "kernel": kind, "kernel_ms_per_launch": round(t_meas * 1e3, 4),
+            "launches": n_launch,
+            "algorithmic_bytes_per_launch": round(alg_bytes),
+            "algorithmic_flops_per_launch": round(alg_flops),
+            "bytes_per_station_sample": bytes_per_ss, "flops_per_station_sample": flops_per_ss,
+            "arithmetic_intensity_flop_per_byte": round(flops_per_ss / bytes_per_ss, 2),
+            "ridge_flop_per_byte": round(FP32_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS, 2),
+            "source_hash": src_hash,
+            ("alu" if bound == "hbm" else "hbm"): side}
 
 
 def cpu_model() -> str:
@@ -190,6 +232,42 @@ def rocpd_summary(db_path: str) -> str:
     return "\n".join(lines)
 
 
+def _counter_means(db_path: str, counter: str) -> dict:
+    """Mean value per dispatch of one counter, per short kernel name (rocpd database)."""
+    import sqlite3
+    cur = sqlite3.connect(db_path).cursor()
+    agg = {}
+    for kn, cn, val in cur.execute("select kernel_name, counter_name, value "
+                                   "from counters_collection"):
+        if cn != counter:
+            continue
+        e = agg.setdefault(short_kernel_name(kn), [0, 0.0])
+        e[0] += 1
+        e[1] += val
+    return {k: tot / n for k, (n, tot) in agg.items()}
+
+
+def traffic_json(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db: str,
+                 ss_per_launch: float, kernels: dict) -> dict:
+    """HBM bytes per station-sample of each kernel kind from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for a
+    plain 1 GiB device copy (which reads and writes 1 GiB)."""
+    copy_kib = (1 << 30) / 1024.0
+    cf = _counter_means(copy_fetch_db, "FETCH_SIZE")["__amd_rocclr_copyBuffer"]
+    cw = _counter_means(copy_write_db, "WRITE_SIZE")["__amd_rocclr_copyBuffer"]
+    sf, sw = copy_kib / cf, copy_kib / cw
+    fetch = _counter_means(fetch_db, "FETCH_SIZE")
+    write = _counter_means(write_db, "WRITE_SIZE")
+    out = {"fetch_scale": sf, "write_scale": sw, "ss_per_launch": ss_per_launch}
+    for kind, (name, srcs) in kernels.items():
+        fb = fetch[name] * sf * 1024.0
+        wb = write[name] * sw * 1024.0
+        out[kind] = {"kernel": name, "source_hash": kernel_source_hash(srcs),
+                     "fetch_bytes_per_launch": round(fb), "write_bytes_per_launch": round(wb),
+                     "bytes_per_station_sample": (fb + wb) / ss_per_launch}
+    return out
+
+
 def calibrate_copy():
     import torch
     n = 1 << 30
@@ -288,19 +366,18 @@ def run_c4(a):
     job, desc = make_job("c4")
     xcorr.job_to_device(job, "cuda:0")
     corr = xcorr.Correlator(0)
-    oks = [corr.ingest(st.frames) for st in job.stations]
     res = {}
     for prec in ("fp32", "fp16", "fp8"):
         p = xcorr.PRECISIONS[prec]
-        ws = corr.alloc_workspace(job, precision=p, frame_ok=oks)
+        ws = corr.alloc_workspace(job, precision=p)
         out = corr.alloc_output(job)
         for _ in range(a.warmup):
-            corr.correlate(job, precision=p, out=out, workspace=ws, frame_ok=oks)
+            corr.correlate(job, precision=p, out=out, workspace=ws)
         torch.cuda.synchronize()
-        corr.profile_begin(a.steps * 64 + 64)
+        corr.profile_begin(a.steps * 128 + 64)
         t0 = time.perf_counter()
         for _ in range(a.steps):
-            corr.correlate(job, precision=p, out=out, workspace=ws, frame_ok=oks)
+            corr.correlate(job, precision=p, out=out, workspace=ws)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / a.steps
         prof = corr.profile_end()
@@ -324,45 +401,107 @@ def run_c4(a):
     }
 
 
+def _server_fpb(job, elem_bytes=8, cap=1 << 30):
+    """Frames per block the server gives a request: the library default, with
+    the request's staged spectra capped at 1 GiB (at least 16 frames)."""
+    per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
+    T = _default_fpb(job, elem_bytes)
+    if T * per_frame > cap:
+        T = max(16, cap // per_frame)
+    return int(T)
+
+
 def run_c5(a):
-    """Poisson request trace through the continuous-batching server."""
+    """Poisson request trace through the continuous-batching server, against
+    the same requests run one after another through the plain per-job path;
+    a sample of the served results is checked bit for bit against the same
+    request run alone."""
     import torch
     from paper_1502_06894_amd import xcorr
     from synth import configs
     log("generating the 20-station x 16-stream x 4.5 s pool on the GPU")
     pool = configs.pool_recordings(device="cuda")
     trace = configs.serve_trace(pool, a.requests, rate_hz=a.rate, max_log2_chan=a.max_log2_chan)
-    torch.cuda.synchronize()
-    ss = sum(j.station_samples for _, j in trace)
+    jobs = [j for _, j in trace]
+    ss = sum(j.station_samples for j in jobs)
     span = trace[-1][0]
-    log(f"{len(trace)} requests over {span:.2f} s, offered {ss / span / 1e9:.1f} G ss/s")
+    # outputs allocated up front, so that no allocation runs beside the server
+    outs = [(torch.empty(j.n_subbands, j.n_baselines, j.n_chan, dtype=torch.complex64,
+                         device="cuda"),
+             torch.empty(j.n_subbands, j.n_baselines, dtype=torch.float32, device="cuda"))
+            for j in jobs]
+    torch.cuda.synchronize()
+    log(f"{len(trace)} requests over {span:.2f} s, offered {ss / span / 1e9:.1f} G ss/s, "
+        f"outputs {sum(v.numel() * 8 for v, _ in outs) / 1e9:.1f} GB")
     slots = a.lanes or 16      # more slots than C3's lanes: small requests need not queue
     srv = xcorr.Server(0, hbm_budget_bytes=a.budget_gb << 30, max_slots=slots)
     tickets = []
     t0 = time.perf_counter()
-    for arr, job in trace:
+    for (arr, job), o in zip(trace, outs):
         now = time.perf_counter() - t0
         if arr > now:
             time.sleep(arr - now)
-        tickets.append(srv.submit(job)[0])
-    rcs = [srv.wait(t) for t in tickets]
+        tickets.append(srv.submit(job, out=o)[0])
+    rcs = []
+    for k, t in enumerate(tickets):
+        rcs.append(srv.wait(t))
+        if (k + 1) % 250 == 0:
+            log(f"  {k + 1} requests served")
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
     log(f"served {st['completed']} requests in {wall:.2f} s: p50 {st['p50_ms']:.1f} ms, "
         f"p99 {st['p99_ms']:.1f} ms, {st['station_samples_per_s'] / 1e9:.1f} G ss/s")
+
+    # the same requests through the plain per-job path, one after another
+    # (library defaults, one workspace sized for the largest request)
+    corr = xcorr.Correlator(0)
+    ws = torch.empty(max(corr.workspace_bytes(j) for j in jobs), dtype=torch.uint8, device="cuda")
+    o1 = (torch.empty(max(v.numel() for v, _ in outs), dtype=torch.complex64, device="cuda"),
+          torch.empty(max(w.numel() for _, w in outs), dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k, j in enumerate(jobs):
+        v = o1[0][:j.n_subbands * j.n_baselines * j.n_chan].view(j.n_subbands, j.n_baselines,
+                                                                  j.n_chan)
+        w = o1[1][:j.n_subbands * j.n_baselines].view(j.n_subbands, j.n_baselines)
+        corr.correlate(j, out=(v, w), workspace=ws)
+        if (k + 1) % 250 == 0:
+            torch.cuda.synchronize()
+            log(f"  per-job path: {k + 1} requests")
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t1
+    loop_gss = ss / t_loop / 1e9
+    log(f"per-job path: {t_loop:.2f} s, {loop_gss:.1f} G ss/s")
+
+    # alone vs in the mix: every k-th served request run alone with the
+    # server's block size must give the same bits
+    n_check = min(a.check_jobs, len(jobs))
+    idx = np.linspace(0, len(jobs) - 1, n_check).round().astype(int).tolist()
+    same = 0
+    for i in idx:
+        j = jobs[i]
+        v, w = corr.correlate(j, frames_per_block=_server_fpb(j))
+        same += int(torch.equal(v, outs[i][0]) and torch.equal(w, outs[i][1]))
+    torch.cuda.synchronize()
+    log(f"alone == in the mix, bit for bit: {same} of {n_check} sampled requests")
+    served = st["station_samples_per_s"] / 1e9
     return {
-        "metric": "correlated station-samples/s", "value": round(st["station_samples_per_s"] / 1e9, 2),
+        "metric": "correlated station-samples/s", "value": round(served, 2),
         "unit": "G station-samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(wall * 1e3, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"C5: Poisson trace, {len(trace)} requests at {a.rate:g}/s "
                                f"(stations 3-20, subbands 1-16, channels 256-{2 ** a.max_log2_chan}, "
                                f"0.1-4 s) over the device-resident pool",
-                   "slots": slots, "hbm_budget_gb": a.budget_gb},
+                   "slots": slots, "hbm_budget_gb": a.budget_gb,
+                   "station_samples": ss},
         "latency_ms": {"p50": round(st["p50_ms"], 2), "p99": round(st["p99_ms"], 2),
                        "mean": round(st["mean_ms"], 2)},
         "offered_g_per_s": round(ss / span / 1e9, 2),
+        "per_job_path": {"value": round(loop_gss, 2), "seconds": round(t_loop, 3)},
+        "served_over_per_job": round(served / loop_gss, 3),
+        "alone_equals_mix": {"checked": n_check, "identical": same},
         "completed": st["completed"], "failed": st["failed"],
         "all_ok": all(rc == 0 for rc in rcs),
     }
@@ -444,8 +583,8 @@ def run_fringe(a):
                      "kernel": "fringe (delay FFT + rate FFT)",
                      "kernel_ms_per_launch": round(ms_k, 4),
                      "algorithmic_bytes_per_launch": bytes_,
-                     "alu": {"achieved": round(alu, 2), "peak": FP32_VECTOR_PEAK_TFS,
-                             "unit": "TFLOP/s", "frac": round(alu / FP32_VECTOR_PEAK_TFS, 4),
+                     "alu": {"achieved": round(alu, 2), "peak": FP32_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(alu / FP32_PEAK_TFLOPS, 4),
                              "flops_per_launch": flops}},
         "planted_peak_fraction": ok,
         "cpu_baseline": cpu,
@@ -524,18 +663,35 @@ def main():
                     help="c1/c2: correct the space station's delay drift inside frames")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--rocpd-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
+    ap.add_argument("--traffic-json", nargs=4,
+                    metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
+                    help="write profiles/hbm_counters.json from FETCH_SIZE / WRITE_SIZE runs of "
+                         "the C2 workload and of --calibrate-copy, and exit")
+    ap.add_argument("--ss-per-launch", type=float, default=671088640.0,
+                    help="--traffic-json: station-samples per F / X launch of the profiled run "
+                         "(C2: 10 stations x 16 inputs x 2048 frames x 2048 samples)")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
                     help="c4: precision reported as the value")
     ap.add_argument("--jobs", type=int, default=64, help="c3: number of jobs")
     ap.add_argument("--lanes", type=int, default=0,
                     help="c3: concurrent lanes (default 8); c5: server slots (default 16)")
-    ap.add_argument("--requests", type=int, default=200, help="c5: requests in the trace")
+    ap.add_argument("--requests", type=int, default=2000, help="c5: requests in the trace")
+    ap.add_argument("--check-jobs", type=int, default=50,
+                    help="c5: served requests re-run alone and compared bit for bit")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: mean arrival rate (1/s)")
     ap.add_argument("--max-log2-chan", type=int, default=14, help="c5: largest log2(channels)")
     ap.add_argument("--budget-gb", type=int, default=96, help="c5: server HBM budget (GiB)")
     a = ap.parse_args()
     if a.rocpd_summary:
         print(rocpd_summary(a.rocpd_summary))
+        return
+    if a.traffic_json:
+        d = traffic_json(*a.traffic_json, a.ss_per_launch,
+                         {"fstage": ("xc::k_fstage<2048, 8, 0>", F_SOURCES),
+                          "xmac": ("xc::k_xmac_ring<20>", X_SOURCES)})
+        with open(os.path.join(ROOT, "profiles", "hbm_counters.json"), "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d, indent=1))
         return
     if a.gpus != 1:
         print("bench.py measures one GPU: the correlation path is built and measured on a "
@@ -570,14 +726,15 @@ def main():
     log(f"workload ready in {time.perf_counter() - t:.1f} s: {job.station_samples:.3e} "
         f"station-samples per step")
     corr = xcorr.Correlator(0)
-    oks = [corr.ingest(st.frames) for st in job.stations]
-    ws = corr.alloc_workspace(job, frames_per_block=a.frames_per_block, frame_ok=oks)
+    # every step runs the whole path, A0 included: the library checks each
+    # recording frame's sync word (xc_ingest's kernel) inside the call
+    ws = corr.alloc_workspace(job, frames_per_block=a.frames_per_block)
     out = corr.alloc_output(job)
     stream = torch.cuda.current_stream()
 
     def step():
         corr.correlate(job, frames_per_block=a.frames_per_block, out=out, workspace=ws,
-                       frame_ok=oks, stream=stream)
+                       stream=stream)
 
     for i in range(a.warmup):
         step()
@@ -588,7 +745,8 @@ def main():
           for _ in range(a.steps)]
     T = a.frames_per_block or _default_fpb(job)
     blocks = -(-job.n_frames // T)
-    corr.profile_begin(max_launches=a.steps * (4 * blocks + 4) + 16)   # delays, F (+ drift pass), X
+    # per block: delays, F (+ drift pass), X; per call: ingest per station, zero, finalise
+    corr.profile_begin(max_launches=a.steps * (4 * blocks + job.n_stations + 4) + 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
@@ -607,38 +765,19 @@ def main():
         if n:
             log(f"  kernel {k:9s}: {ms / a.steps:8.3f} ms/step over {n // a.steps} launches")
 
-    # roofline of the dominant kernel (algorithmic bytes per station-sample)
-    per_ss = {"fstage": (4.25, F_SOURCES), "xmac": (4.0, X_SOURCES)}
+    # roofline of the dominant kernel: algorithmic bytes and flops per
+    # station-sample (F stage: 0.25 B of 2-bit input + 4 B of FP32 spectra out;
+    # 5 log2 N flops of FFT + ~10 of fringe rotation and phasor generation + ~5
+    # of fractional-delay correction.  X stage: 4 B of spectra in; 2 (M + 1)
+    # flops of complex multiply-accumulate)
+    per_ss = {"fstage": (4.25, 5.0 * math.log2(job.N) + 15.0, F_SOURCES),
+              "xmac": (4.0, 2.0 * (job.M + 1), X_SOURCES)}
     dom = max(per_ss, key=lambda k: prof[k][0])
-    bytes_per_ss, srcs = per_ss[dom]
-    ms_tot, n_launch = prof[dom]
-    alg_bytes = bytes_per_ss * ss * a.steps
-    achieved = alg_bytes / (ms_tot * 1e-3) / 1e9
-    src_hash = kernel_source_hash(srcs)
-    # the same kernel against the vector-ALU peak: algorithmic flops per
-    # station-sample (FFT 5 log2 N, rotation 2, fractional delay 3; X stage 2 (M + 1))
-    flops_per_ss = {"fstage": 5.0 * math.log2(job.N) + 5.0, "xmac": 2.0 * (job.M + 1)}[dom]
-    alu_achieved = flops_per_ss * ss * a.steps / (ms_tot * 1e-3) / 1e12
-    hbm_view = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": round(alg_bytes / n_launch),
-                "bytes_per_station_sample": bytes_per_ss}
-    alu_view = {"achieved": round(alu_achieved, 2), "peak": FP32_VECTOR_PEAK_TFS,
-                "unit": "TFLOP/s", "frac": round(alu_achieved / FP32_VECTOR_PEAK_TFS, 4),
-                "algorithmic_flops_per_launch": round(flops_per_ss * ss * a.steps / n_launch),
-                "flops_per_station_sample": flops_per_ss}
-    # the roof that binds: the vector ALU when the kernel's arithmetic intensity
-    # lies right of the ridge point (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B), else HBM;
-    # the other view is kept beside it (the metric also asks for % of HBM)
-    ridge = FP32_VECTOR_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    alu_bound = flops_per_ss / bytes_per_ss > ridge
-    main_view, side = (alu_view, "hbm") if alu_bound else (hbm_view, "alu")
-    roof = {"bound": "alu" if alu_bound else "hbm", **main_view,
-            "traffic": traffic_from_profile(dom, src_hash, 0), "kernel": dom,
-            "kernel_ms_per_launch": round(ms_tot / n_launch, 4),
-            "arithmetic_intensity_flop_per_byte": round(flops_per_ss / bytes_per_ss, 2),
-            "source_hash": src_hash,
-            side: alu_view if side == "alu" else hbm_view}
+    roof = roofline(dom, *per_ss[dom], prof[dom], ss * a.steps)
+    # the whole staged path against HBM: every station-sample moves 8.25 B
+    roof["path_hbm"] = {"achieved": round(8.25 * value, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(8.25 * value / HBM_PEAK_GBS, 4),
+                        "bytes_per_station_sample": 8.25}
     kernels = {k: {"ms_per_step": round(ms / a.steps, 3), "launches_per_step": n // a.steps}
                for k, (ms, n) in prof.items() if n}
 

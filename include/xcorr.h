@@ -274,7 +274,9 @@ int  xc_server_create(xc_server** out, int hip_device, size_t hbm_budget_bytes,
 /* XC_E_NOMEM if the job's footprint exceeds the whole budget; XC_E_INVAL or
  * XC_E_RANGE for an invalid job; otherwise queues it and sets *ticket. */
 int  xc_server_submit(xc_server* srv, const xc_job* job, uint64_t* ticket);
-/* *done = 1 once the request finished; returns its result code then. */
+/* *done = 1 once the request finished; returns its result code then.  Once
+ * poll or wait has reported a request finished, the server forgets its ticket:
+ * later calls with it return XC_E_INVAL. */
 int  xc_server_poll(xc_server* srv, uint64_t ticket, int32_t* done);
 /* Block until done (returns its result code) or XC_E_TIMEOUT after timeout_ms (< 0: no limit). */
 int  xc_server_wait(xc_server* srv, uint64_t ticket, int32_t timeout_ms);

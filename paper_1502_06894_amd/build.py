@@ -1,6 +1,8 @@
 """Build libxcorr.so (all HIP sources, gfx950) in the package directory.
 
-hipcc cross-compiles without a GPU.  Every call rebuilds.
+hipcc cross-compiles without a GPU.  Every call rebuilds: each source is
+compiled to an object in parallel (under _build/ at the repository root),
+then the objects are linked into the shared library.
 """
 from __future__ import annotations
 
@@ -9,14 +11,16 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libxcorr.so")
+OBJ = os.path.join(ROOT, "_build")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-function",
     # no packed FP32 instructions (hipcc's host pass warns that it does not
     # know the feature; that is harmless)
@@ -32,16 +36,26 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *srcs, "-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
+        raise RuntimeError(f"hipcc failed: {cmd[-1]}")
+
+
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    os.makedirs(OBJ, exist_ok=True)
+    objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in srcs]
+    cc = hipcc()
+    n = jobs or min(len(srcs), os.cpu_count() or 1, 16)
+    with ThreadPoolExecutor(max_workers=n) as ex:
+        list(ex.map(lambda so: _run([cc, *HIPCC_FLAGS, "-c", so[0], "-o", so[1]], verbose),
+                    zip(srcs, objs)))
+    tmp = LIB + ".tmp"
+    _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -549,6 +549,7 @@ __global__ void __launch_bounds__(256)
     k_fbig_b(const DevJob* __restrict__ job, const DelayRec* __restrict__ drec,
              const float2* __restrict__ tw, const float2* __restrict__ Z,
              void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf) {
+  static_assert(OUT != kOutF32, "FP32 spectra at N = 32768 come from k_fhalf");
   constexpr int T = FftPlan<kBigN2>::T, E = FftPlan<kBigN2>::E;
   constexpr int G = 256 / T;
   extern __shared__ float2 lds_all[];
@@ -810,8 +811,7 @@ static hipError_t launch_big(const DevJob* job, int n_stations, int n_inputs,
     hipLaunchKernelGGL(k_fbig_b<kOutF8>, grid, dim3(256), lds, s, job, drec, tw, Z, spec,
                        scale_exp, nf);
   else
-    hipLaunchKernelGGL(k_fbig_b<kOutF32>, grid, dim3(256), lds, s, job, drec, tw, Z, spec,
-                       scale_exp, nf);
+    return hipErrorInvalidValue;   // FP32 spectra fold the frame instead (k_fhalf)
   return hipGetLastError();
 }
 

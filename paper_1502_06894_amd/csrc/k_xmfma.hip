@@ -25,33 +25,49 @@ namespace xc {
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
-__global__ void k_scales(const float2* __restrict__ spec, int n_sb, int nf, int M, int n_chan,
-                         int target_log2, int8_t* __restrict__ scale_exp) {
+// Mean square of the four 2-bit levels for Gaussian data quantised at +-0.9816
+// sigma (outer levels with probability 2 Phi(-0.9816) = 0.32630): the expected
+// |Y[k]|^2 / N of an unnormalised FFT of such samples, whatever the rotation.
+constexpr double kLevelPower = 4.304810;
+
+// Per (subband, input, channel): the power-of-two exponent that brings the mean
+// |Y|^2 over the pre-pass frames valid for the input's station to
+// 2^(2 target_log2).  Invalid frames (zero spectra) are left out of the mean;
+// an input with no valid pre-pass frame takes the expected white-noise power
+// N kLevelPower of 2-bit data.
+__global__ void k_scales(const float2* __restrict__ spec, const DelayRec* __restrict__ drec,
+                         int n_sb, int nf, int M, int P, int n_chan, int target_log2,
+                         int8_t* __restrict__ scale_exp) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;   // (sb, m, k)
   const size_t total = (size_t)n_sb * M * n_chan;
   if (i >= total) return;
   const int k = (int)(i % n_chan);
   const int m = (int)((i / n_chan) % M);
   const int sb = (int)(i / ((size_t)n_chan * M));
+  const DelayRec* rec = drec + (size_t)(m / P) * nf;
   double acc = 0.0;
+  int n_valid = 0;
   for (int f = 0; f < nf; ++f) {
+    if (!rec[f].valid) continue;
     const float2 y = spec[(((size_t)sb * nf + f) * M + m) * n_chan + k];
     acc += (double)y.x * y.x + (double)y.y * y.y;
+    ++n_valid;
   }
+  const double power = n_valid > 0 ? acc / n_valid : 2.0 * n_chan * kLevelPower;
   int e = 0;
-  if (acc > 0.0) {
-    const double l2 = 0.5 * log2(acc / nf);            // log2 of the RMS magnitude
+  if (power > 0.0) {
+    const double l2 = 0.5 * log2(power);                // log2 of the RMS magnitude
     e = (int)lrint((double)target_log2 - l2);
     e = e < -100 ? -100 : (e > 100 ? 100 : e);
   }
   scale_exp[i] = (int8_t)e;
 }
 
-hipError_t launch_scales(const float2* spec, int n_subbands, int nf, int M, int n_chan,
-                         int target_log2, int8_t* scale_exp, hipStream_t s) {
+hipError_t launch_scales(const float2* spec, const DelayRec* drec, int n_subbands, int nf, int M,
+                         int P, int n_chan, int target_log2, int8_t* scale_exp, hipStream_t s) {
   const size_t total = (size_t)n_subbands * M * n_chan;
   hipLaunchKernelGGL(k_scales, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, spec,
-                     n_subbands, nf, M, n_chan, target_log2, scale_exp);
+                     drec, n_subbands, nf, M, P, n_chan, target_log2, scale_exp);
   return hipGetLastError();
 }
 

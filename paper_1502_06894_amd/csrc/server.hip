@@ -278,13 +278,24 @@ int xc_server_submit(xc_server* s, const xc_job* job, uint64_t* ticket) {
   return XC_OK;
 }
 
+// A finished request whose result has been reported: forget its ticket and
+// release its event (caller holds mu).  Without this a long-running server
+// would keep every request it ever served.
+static int retire(xc_server* s, std::map<uint64_t, std::shared_ptr<Request>>::iterator it) {
+  const int rc = it->second->rc;
+  if (it->second->done_ev) (void)hipEventDestroy(it->second->done_ev);
+  it->second->done_ev = nullptr;
+  s->all.erase(it);
+  return rc;
+}
+
 int xc_server_poll(xc_server* s, uint64_t ticket, int32_t* done) {
   if (!s || !done) return XC_E_INVAL;
   std::lock_guard<std::mutex> g(s->mu);
   auto it = s->all.find(ticket);
   if (it == s->all.end()) return XC_E_INVAL;
   *done = it->second->state == State::Done ? 1 : 0;
-  return *done ? it->second->rc : XC_OK;
+  return *done ? retire(s, it) : XC_OK;
 }
 
 int xc_server_wait(xc_server* s, uint64_t ticket, int32_t timeout_ms) {
@@ -298,7 +309,9 @@ int xc_server_wait(xc_server* s, uint64_t ticket, int32_t timeout_ms) {
     s->cv_done.wait(lk, pred);
   else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred))
     return XC_E_TIMEOUT;
-  return r->rc;
+  // another thread may have retired the ticket while this one waited
+  it = s->all.find(ticket);
+  return it == s->all.end() ? r->rc : retire(s, it);
 }
 
 int xc_server_cancel(xc_server* s, uint64_t ticket) {

@@ -65,9 +65,11 @@ hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,
 size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf, int out);
 // Power-of-two exponents per (subband, input, channel) that bring the mean
 // |Y|^2 of the first nf frames (FP32 spectra [n_sb][nf][M][n_chan]) to
-// target_log2 (i.e. RMS 2^target_log2); 0 when a channel has no power.
-hipError_t launch_scales(const float2* spec, int n_subbands, int nf, int M, int n_chan,
-                         int target_log2, int8_t* scale_exp, hipStream_t s);
+// target_log2 (i.e. RMS 2^target_log2), averaged over the frames that drec
+// ([n_stations][nf], input m = s P + p) marks valid; an input with no valid
+// frame among them takes the expected power of white 2-bit data.
+hipError_t launch_scales(const float2* spec, const DelayRec* drec, int n_subbands, int nf, int M,
+                         int P, int n_chan, int target_log2, int8_t* scale_exp, hipStream_t s);
 // A7: X stage on MFMA for the low-precision spectra (out = kOutF16 or kOutF8),
 // M <= 32; accumulates into the same FP64 slots as the FP32 X stage.
 hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_subbands,

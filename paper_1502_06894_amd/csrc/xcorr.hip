@@ -284,8 +284,9 @@ int enqueue_job(xc_ctx* c, const xc_setup* s, const xc_station* st, const xc_out
                              reinterpret_cast<float2*>(arena + L.scratch), stream);
       });
     if (e == hipSuccess)
-      e = launch_scales(static_cast<const float2*>(spec), nsb, L.n_scale, M, s->n_chan,
-                        L.out == kOutF16 ? kF16TargetLog2 : kF8TargetLog2, sexp, stream);
+      e = launch_scales(static_cast<const float2*>(spec), drec, nsb, L.n_scale, M, s->n_pols,
+                        s->n_chan, L.out == kOutF16 ? kF16TargetLog2 : kF8TargetLog2, sexp,
+                        stream);
     if (e != hipSuccess) return hip_fail(c, e, "scales");
   }
   // Blocks of L.T frames.  Overlapped: block b uses buffer p = b mod 2; its F

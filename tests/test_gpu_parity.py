@@ -279,6 +279,27 @@ def test_bad_frames_and_out_of_buffer(xc, corr):
     assert rel_l2(vis.cpu().numpy(), V) < TOL
 
 
+def test_n32768_input_groups_and_invalid_frames(xc, corr):
+    """N = 32768 (the folded FP32 F stage, tasks over groups of four inputs):
+    six inputs per station (a group of four and one of two), a bad sync word
+    on one station and the last FFT frame of another outside its recording."""
+    job = configs.small_job(n_stations=3, n_subbands=3, n_pols=2, n_chan=16384, C=8, n_frames=6,
+                            seed=41)
+    job.stations[0].frames = job.stations[0].frames.clone()
+    job.stations[0].frames[3, 0] = 0                   # bad sync in recording frame 3
+    job.stations[2].frames = job.stations[2].frames[:-3].contiguous()   # the end is cut
+    V, W = fx.correlate(job, threads=8)
+    assert W.min() < job.n_frames - 1 and W.max() == job.n_frames
+    _on_gpu(xc, job)
+    vis, w = corr.correlate(job)
+    assert np.array_equal(w.cpu().numpy(), W.astype(np.float32))
+    vis = vis.cpu().numpy()
+    for sb in range(job.n_subbands):
+        for bl in range(job.n_baselines):
+            if W[sb, bl] > 0:
+                assert rel_l2(vis[sb, bl], V[sb, bl]) < TOL, (sb, bl)
+
+
 def test_invalid_frames_across_weight_chunks(xc, corr):
     """One 5000-frame block (the default for a job this small), so the pair
     weights are counted over three 2048-frame chunks; bad sync words and the

@@ -60,7 +60,8 @@ def _c4_shaped():
     dict(n_stations=6, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=75),
     None,
     dict(n_stations=4, n_subbands=5, n_pols=1, n_chan=4096, C=8, n_frames=24, realistic=False),
-], ids=["m32", "dualpol", "c4shape", "lean_5in"])
+    dict(n_stations=3, n_subbands=2, n_pols=1, n_chan=16384, C=2, n_frames=5),
+], ids=["m32", "dualpol", "c4shape", "lean_5in", "n32768"])
 def test_mfma_precision_bound(xc, corr, prec, kw):
     job = _c4_shaped() if kw is None else configs.small_job(**kw, seed=17)
     V, W = fx.correlate(job, threads=8)
@@ -82,6 +83,45 @@ def test_mfma_precision_bound(xc, corr, prec, kw):
           f"max {cross.max():.3e}; per-baseline relative L2: median {np.median(rel):.3e}, "
           f"max {rel.max():.3e}")
     assert worst <= bound
+
+
+def _late_start(job, station, first_valid):
+    """Cut the start of a station's recording so that its FFT frames before
+    `first_valid` fall outside it (and frame `first_valid` stays inside)."""
+    from synth import format as fmt
+    st = job.stations[station]
+    spf = fmt.samples_per_frame(job.n_streams)
+    n_int, _ = fx.frame_delays(st.delay_poly, job.sub_start, job.N, job.fs_hz,
+                               np.array([first_valid - 1, first_valid]))
+    base = job.sub_start + np.array([first_valid - 1, first_valid]) * job.N + n_int - st.first_sample
+    k = int(base[0]) // spf + 1               # recording frames to drop
+    assert k * spf > base[0] and k * spf <= base[1]
+    st.frames = st.frames[k:].contiguous()
+    st.first_sample += k * spf
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp8"])
+def test_mfma_scales_from_valid_frames(xc, corr, prec):
+    """Channel scales come from the pre-pass frames valid for each station:
+    station 1's recording starts after the 64 scale frames (no valid one: the
+    expected white-noise level is used) and station 2's after 62 of them.
+    Unscaled, the spectra of an N = 32768 frame (RMS ~375) would saturate
+    e4m3 (max 448) on ~9 % of their components."""
+    job = configs.small_job(n_stations=3, n_subbands=1, n_pols=1, n_chan=16384, C=2,
+                            n_frames=80, seed=23)
+    _late_start(job, 1, 66)
+    _late_start(job, 2, 62)
+    V, W = fx.correlate(job, threads=8)
+    assert W[0, fx.baseline_index(1, 1, 3)] == 14 and W[0, fx.baseline_index(2, 2, 3)] == 18
+    xc.job_to_device(job)
+    vis, w = corr.correlate(job, precision=xc.PRECISIONS[prec])
+    torch.cuda.synchronize()
+    vis, w = vis.cpu().numpy(), w.cpu().numpy()
+    assert np.array_equal(w, W.astype(np.float32))
+    worst, _ = _norm_err(vis, V, job)
+    u = U[prec]
+    print(f"\n{prec} late-start stations: max |dV|/sqrt(AiAj) = {worst:.3e}")
+    assert worst <= 1.1 * (2 * u + u * u)
 
 
 def test_mfma_rejects_more_than_32_inputs(xc, corr):
