@@ -30,10 +30,18 @@ typedef float float16_t __attribute__((ext_vector_type(16)));
 // |Y[k]|^2 / N of an unnormalised FFT of such samples, whatever the rotation.
 constexpr double kLevelPower = 4.304810;
 
+// Valid pre-pass frames an input needs for its own per-channel scales: a mean
+// |Y|^2 over fewer frames is too noisy (over 2 frames a channel's estimate is
+// below 1/100 of its power with probability ~2e-4, which over 16384 channels
+// would push a few channels 10x above the target level, into e4m3
+// saturation); with 16 the estimate stays within a factor 4 in power.
+constexpr int kMinScaleFrames = 16;
+
 // Per (subband, input, channel): the power-of-two exponent that brings the mean
 // |Y|^2 over the pre-pass frames valid for the input's station to
 // 2^(2 target_log2).  Invalid frames (zero spectra) are left out of the mean;
-// an input with no valid pre-pass frame takes the expected white-noise power
+// an input with fewer than kMinScaleFrames valid pre-pass frames (all of them,
+// when the pre-pass is shorter) takes the expected white-noise power
 // N kLevelPower of 2-bit data.
 __global__ void k_scales(const float2* __restrict__ spec, const DelayRec* __restrict__ drec,
                          int n_sb, int nf, int M, int P, int n_chan, int target_log2,
@@ -53,7 +61,8 @@ __global__ void k_scales(const float2* __restrict__ spec, const DelayRec* __rest
     acc += (double)y.x * y.x + (double)y.y * y.y;
     ++n_valid;
   }
-  const double power = n_valid > 0 ? acc / n_valid : 2.0 * n_chan * kLevelPower;
+  const bool own = n_valid > 0 && n_valid >= min(nf, kMinScaleFrames);
+  const double power = own ? acc / n_valid : 2.0 * n_chan * kLevelPower;
   int e = 0;
   if (power > 0.0) {
     const double l2 = 0.5 * log2(power);                // log2 of the RMS magnitude

@@ -103,10 +103,11 @@ def _late_start(job, station, first_valid):
 @pytest.mark.parametrize("prec", ["fp16", "fp8"])
 def test_mfma_scales_from_valid_frames(xc, corr, prec):
     """Channel scales come from the pre-pass frames valid for each station:
-    station 1's recording starts after the 64 scale frames (no valid one: the
-    expected white-noise level is used) and station 2's after 62 of them.
-    Unscaled, the spectra of an N = 32768 frame (RMS ~375) would saturate
-    e4m3 (max 448) on ~9 % of their components."""
+    station 1's recording starts after the 64 scale frames and station 2's
+    after 62 of them (two valid frames: too few for a per-channel estimate);
+    both take the expected white-noise level.  Unscaled, the spectra of an
+    N = 32768 frame (RMS ~375) would saturate e4m3 (max 448) on ~9 % of their
+    components; scaled from two frames, a few of 16384 channels would."""
     job = configs.small_job(n_stations=3, n_subbands=1, n_pols=1, n_chan=16384, C=2,
                             n_frames=80, seed=23)
     _late_start(job, 1, 66)
