@@ -154,6 +154,23 @@ size_t xc_workspace_bytes(const xc_ctx* ctx, const xc_setup* setup, const xc_sta
 int xc_correlate_subint(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
                         const xc_output* out, void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): xc_correlate_subint
+ * without a workspace argument.  The library's own fixed device scratch of
+ * xc_noalloc_scratch_bytes() (256 MiB, one per GPU the library runs on,
+ * held until the process ends) takes the workspace's place;
+ * the call allocates nothing.  With frames_per_block = 0 (setup and tuning)
+ * the library picks the largest block whose layout fits the scratch;
+ * otherwise a layout that does not fit returns XC_E_NOMEM, as does a job
+ * whose one-frame blocks do not fit.  Every call on a GPU shares that GPU's
+ * scratch: calls in order on one stream are safe, calls that overlap on one
+ * GPU (other streams, other threads, other contexts) race.  Results equal
+ * xc_correlate_subint's at the same frames per block.  Async on `stream`.
+ * Errors as for xc_correlate_subint. */
+int xc_correlate_subint_noalloc(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
+                                const xc_output* out, void* stream);
+size_t xc_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------- test taps */
 /* Same kernels as the correlation path, results copied to host; synchronous. */
 /* Delay model per station and frame: n_int [S][F], d_frac [S][F], valid [S][F],

@@ -52,6 +52,7 @@ struct xc_ctx {
   std::vector<xc::Timed> prof;
   size_t prof_used = 0;
   float2* d_tw = nullptr;                    // FFT twiddles, kTwiddleN entries
+  int scratch_rc = 0;                        // lookup of the allocation-free scratch (hipError_t)
   unsigned char* h_stage = nullptr;          // kSlots x kSlotBytes pinned
   hipEvent_t ev[xc::kSlots] = {};
   int next_slot = 0;

@@ -2,9 +2,36 @@
 // upload and launch sequencing of the correlation path.
 #include <math.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "xc_runtime.h"
 
 namespace xc {
+
+// ---------------------------------------------------------------- allocation-free scratch
+// Workspace of xc_correlate_subint_noalloc: a fixed array in the library's
+// device code object, one copy per GPU, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory, so it is never
+// handed to a kernel or a copy: xc_create looks up each device's address once
+// (with that device current) and every use goes through that address.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+static std::atomic<unsigned char*> g_scratch_addr[kScratchDevices];
+static std::mutex g_scratch_mu;
+
+// The current device's address of `scratch` (caller has made `dev` current).
+static hipError_t scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  if (g_scratch_addr[dev].load()) return hipSuccess;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_addr[dev].load()) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) g_scratch_addr[dev].store(static_cast<unsigned char*>(p));
+  return e != hipSuccess ? e : p ? hipSuccess : hipErrorInvalidSymbol;
+}
 
 int fail(xc_ctx* c, int code, const char* fmt, ...) {
   if (c) {
@@ -469,6 +496,7 @@ int xc_create(xc_ctx** out, int hip_device) {
     e = hipMemcpy(c->d_tw, tw.data(), sizeof(float2) * kTwiddleN, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&c->h_stage, (size_t)kSlots * kSlotBytes, hipHostMallocDefault);
+  if (e == hipSuccess) c->scratch_rc = (int)scratch_lookup(hip_device);
   for (int k = 0; k < kSlots && e == hipSuccess; ++k)
     e = hipEventCreateWithFlags(&c->ev[k], hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -553,6 +581,66 @@ int xc_correlate_subint(xc_ctx* c, const xc_setup* s, const xc_station* st, cons
   return enqueue_job(c, s, st, out, reinterpret_cast<const DevJob*>(p.desc), p.arena, p.L, p.tu,
                      stream, p.L.nbuf == 2 ? c->xstream : nullptr);
 }
+
+int xc_correlate_subint_noalloc(xc_ctx* c, const xc_setup* s, const xc_station* st,
+                                const xc_output* out, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!c) return XC_E_INVAL;
+  if (!out || !out->vis || !out->weight) return fail(c, XC_E_INVAL, "output is NULL");
+  int rc = validate(c, s, st);
+  if (rc != XC_OK) return rc;
+  unsigned char* base =
+      c->device >= 0 && c->device < kScratchDevices ? g_scratch_addr[c->device].load() : nullptr;
+  if (!base)
+    return fail(c, XC_E_HIP, "allocation-free scratch unavailable on device %d: %s", c->device,
+                hipGetErrorString((hipError_t)c->scratch_rc));
+  xc_tuning tu = effective_tuning(c, s);
+  tu.block_overlap = 1;   // one block buffer: no second stream, no second arena
+  xc_setup q = *s;
+  auto need = [&](const Layout& L) { return align_up(L.desc_bytes) + L.total; };
+  Layout L = layout_of(&q, st, tu);
+  if (need(L) > kScratchBytes) {
+    if (s->frames_per_block > 0 || tu.frames_per_block > 0)
+      return fail(c, XC_E_NOMEM,
+                  "allocation-free call: %zu bytes needed at %d frames per block, the scratch "
+                  "holds %zu",
+                  need(L), L.T, kScratchBytes);
+    // the largest block that fits: halve, then search between T and 2 T
+    int hi = L.T, lo = 0;
+    for (int T = L.T / 2; T >= 1; T /= 2) {
+      q.frames_per_block = T;
+      if (need(layout_of(&q, st, tu)) <= kScratchBytes) {
+        lo = T;
+        break;
+      }
+      hi = T;
+    }
+    if (lo == 0)
+      return fail(c, XC_E_NOMEM,
+                  "allocation-free call: even one frame per block needs more than the %zu-byte "
+                  "scratch",
+                  kScratchBytes);
+    while (hi - lo > 1) {
+      const int mid = lo + (hi - lo) / 2;
+      q.frames_per_block = mid;
+      if (need(layout_of(&q, st, tu)) <= kScratchBytes)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    q.frames_per_block = lo;
+    L = layout_of(&q, st, tu);
+  }
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  unsigned char* desc = base;
+  unsigned char* arena = base + align_up(L.desc_bytes);
+  rc = upload_desc(c, &q, st, L, desc, arena, stream);
+  if (rc != XC_OK) return rc;
+  return enqueue_job(c, &q, st, out, reinterpret_cast<const DevJob*>(desc), arena, L, tu, stream);
+}
+
+size_t xc_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
   if (!c || !t) return XC_E_INVAL;

@@ -111,6 +111,9 @@ def load_library() -> C.CDLL:
             "xc_workspace_bytes": (C.c_size_t, [P, C.POINTER(XcSetup), C.POINTER(XcStation)]),
             "xc_correlate_subint": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
                                               C.POINTER(XcOutput), P, C.c_size_t, P]),
+            "xc_correlate_subint_noalloc": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
+                                                      C.POINTER(XcOutput), P]),
+            "xc_noalloc_scratch_bytes": (C.c_size_t, []),
             "xc_debug_delays": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation), P, P, P, P,
                                           P, C.c_size_t, P]),
             "xc_debug_unpack": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation), C.c_int32,
@@ -256,6 +259,16 @@ class Correlator:
         self._check(self.lib.xc_correlate_subint(self.ctx, C.byref(m.setup), m.stations,
                                                  C.byref(o), workspace.data_ptr(),
                                                  workspace.numel(), _stream_ptr(stream)))
+        return vis, w
+
+    def correlate_noalloc(self, job, *, precision: int = XC_FP32, frames_per_block: int = 0,
+                          out=None, stream=None, frame_ok=None):
+        """As correlate(), in the library's fixed device scratch (no workspace)."""
+        m = _Marshal(job, precision, frames_per_block, frame_ok)
+        vis, w = out if out is not None else self.alloc_output(job)
+        o = XcOutput(vis.data_ptr(), w.data_ptr())
+        self._check(self.lib.xc_correlate_subint_noalloc(self.ctx, C.byref(m.setup), m.stations,
+                                                         C.byref(o), _stream_ptr(stream)))
         return vis, w
 
     # ------------------------------------------------------------------ batches
