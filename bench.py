@@ -13,6 +13,7 @@ Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py --workload c5        # Poisson request trace through the server
   python bench.py --workload fringe    # delay-rate fringe search over a C2-shaped scan
   python bench.py --workload feed      # feed-angle correction over a C2-shaped scan
+  python bench.py --workload xcross    # X stage: vector FP32 vs MFMA FP16 / e4m3 as inputs grow
   python bench.py --calibrate-copy     # plain device copy of known size, for counter scaling
   python bench.py --rocpd-summary DB   # per-kernel table from a rocprofv3 database
 """
@@ -268,6 +269,24 @@ def traffic_json(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db
     return out
 
 
+def calibrate_read():
+    """Read ceiling: a 4 GiB float32 sum (torch's reduction, HIP events)."""
+    import torch
+    x = torch.ones(1 << 30, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        x.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"read_bytes": 4 << 30, "ms": round(ms, 4),
+                      "gb_per_s": round((4 << 30) / (ms * 1e-3) / 1e9, 1)}))
+
+
 def calibrate_copy():
     import torch
     n = 1 << 30
@@ -286,18 +305,17 @@ def _default_fpb(job, elem_bytes=8):
     return int(min(max(2048, min(65536, (256 << 20) // per_frame)), job.n_frames))
 
 
-def _per_job_fpb(job, elem_bytes=8, cap=1 << 30):
-    """Frames per block the batch executor picks: the library default, with the
-    staged spectra capped at 1 GiB."""
-    per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
-    T = _default_fpb(job, elem_bytes)
-    if T * per_frame > cap:
-        T = max(64, cap // per_frame)
-    return int(T)
+def _batch_fpb(job, tuned_fpb=0, elem_bytes=8):
+    """Frames per block a batch gives a job: the tuned size (else the library
+    default), capped as for every job sharing the device (1 GiB, at least 64)."""
+    T = min(tuned_fpb, job.n_frames) if tuned_fpb else _default_fpb(job, elem_bytes)
+    return _shared_fpb(job, T, 1 << 30, 64, elem_bytes)
 
 
 def run_c3(a):
-    """64 uneven sub-integrations over a device-resident pool: batch vs per-job loop."""
+    """64 uneven sub-integrations over a device-resident pool: the fused batch
+    executor (one persistent F-stage launch per FFT length and round) and the
+    lane executor against the per-job loop, with tile shapes from the autotuner."""
     import torch
     from paper_1502_06894_amd import xcorr
     from synth import configs
@@ -308,9 +326,26 @@ def run_c3(a):
     ss = sum(j.station_samples for j in jobs)
     log(f"{len(jobs)} jobs, {ss:.3e} station-samples")
     corr = xcorr.Correlator(0)
-    # per-job loop, same block sizes as the batch
+    tuned = [{} for _ in jobs]
+    if not a.no_autotune:
+        # candidates that need more than 8 GiB of workspace are skipped
+        wst = torch.empty(8 << 30, dtype=torch.uint8, device="cuda")
+        t0 = time.perf_counter()
+        for k, j in enumerate(jobs):
+            tuned[k] = corr.autotune(j, workspace=wst)
+            if (k + 1) % 8 == 0:
+                log(f"  autotuned {k + 1} jobs ({time.perf_counter() - t0:.1f} s)")
+        del wst
+        torch.cuda.synchronize()
+    picks = {}
+    for t in tuned:
+        key = (f"fpb {t.get('frames_per_block', 0)}, X stage "
+               f"{ {8: 'ring', 4: '4-frame stages', 2: '2-frame stages', 1: 'direct', 0: 'default'}[t.get('xmac_frames_per_stage', 0)] }"
+               + (f" {t['xmac_channels_per_wg']} ch" if t.get("xmac_channels_per_wg") else ""))
+        picks[key] = picks.get(key, 0) + 1
+    fpbs = [_batch_fpb(j, t.get("frames_per_block", 0)) for j, t in zip(jobs, tuned)]
+    # per-job loop at the batch's block sizes
     outs = [corr.alloc_output(j) for j in jobs]
-    fpbs = [_per_job_fpb(j) for j in jobs]
     ws = torch.empty(max(corr.workspace_bytes(j, frames_per_block=f) for j, f in zip(jobs, fpbs)),
                      dtype=torch.uint8, device="cuda")
 
@@ -327,35 +362,50 @@ def run_c3(a):
     t_loop = (time.perf_counter() - t0) / a.steps
     log(f"per-job loop: {t_loop * 1e3:.1f} ms per batch, {ss / t_loop / 1e9:.1f} G ss/s")
     refs = [(v.clone(), w.clone()) for v, w in outs]
+    del ws
     lanes = a.lanes or 8
-    bws = corr.batch_workspace(jobs, n_lanes=lanes)
-    bouts = [corr.alloc_output(j) for j in jobs]
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        corr.correlate_batch(jobs, n_lanes=lanes, graph=True, outs=bouts, workspace=bws,
-                             stream=stream)     # capture
-        stream.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(a.steps):
-            corr.correlate_batch(jobs, n_lanes=lanes, graph=True, outs=bouts, workspace=bws,
-                                 stream=stream)
-        stream.synchronize()
-    t_batch = (time.perf_counter() - t0) / a.steps
-    same = all(torch.equal(v, rv) and torch.equal(w, rw) for (v, w), (rv, rw) in zip(bouts, refs))
-    log(f"batch ({lanes} lanes, graph replay): {t_batch * 1e3:.1f} ms, "
-        f"{ss / t_batch / 1e9:.1f} G ss/s; identical to per-job results: {same}")
+    res = {}
+    for name, lanes_only in (("lanes", True), ("fused", False)):
+        bws = corr.batch_workspace(jobs, n_lanes=lanes, lanes_only=lanes_only)
+        bouts = [corr.alloc_output(j) for j in jobs]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            corr.correlate_batch(jobs, n_lanes=lanes, graph=True, lanes_only=lanes_only,
+                                 outs=bouts, workspace=bws, stream=stream)     # capture
+            stream.synchronize()
+            corr.profile_begin(200000)
+            t0 = time.perf_counter()
+            for _ in range(a.steps):
+                corr.correlate_batch(jobs, n_lanes=lanes, graph=True, lanes_only=lanes_only,
+                                     outs=bouts, workspace=bws, stream=stream)
+            stream.synchronize()
+            tb = (time.perf_counter() - t0) / a.steps
+            prof = corr.profile_end()
+        same = all(torch.equal(v, rv) and torch.equal(w, rw)
+                   for (v, w), (rv, rw) in zip(bouts, refs))
+        res[name] = {"value": round(ss / tb / 1e9, 2), "ms_per_step": round(tb * 1e3, 3),
+                     "over_per_job_loop": round(t_loop / tb, 3), "identical_to_per_job": bool(same),
+                     "workspace_gb": round(bws.numel() / 1e9, 2)}
+        log(f"batch {name} ({lanes} lanes, graph replay): {tb * 1e3:.1f} ms, "
+            f"{ss / tb / 1e9:.1f} G ss/s ({t_loop / tb:.3f}x the per-job loop); identical: {same}")
+        del bws, bouts
+        torch.cuda.synchronize()
+    f = res["fused"]
     return {
-        "metric": "correlated station-samples/s", "value": round(ss / t_batch / 1e9, 2),
+        "metric": "correlated station-samples/s", "value": f["value"],
         "unit": "G station-samples/s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
-        "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"C3: {len(jobs)} uneven sub-integration jobs (stations 2-20, "
                                f"subbands 1-16, channels 128-8192, 0.1-4 s) over a 20-station "
                                f"x 16-stream x 4.5 s device-resident pool",
-                   "lanes": lanes, "graph": True, "station_samples_per_step": ss},
+                   "lanes": lanes, "graph": True, "station_samples_per_step": ss,
+                   "autotuned": not a.no_autotune},
         "per_job_loop": {"value": round(ss / t_loop / 1e9, 2), "ms_per_step": round(t_loop * 1e3, 3)},
-        "batch_over_loop": round(t_loop / t_batch, 3),
-        "identical_to_per_job": bool(same),
+        "fused": f, "lanes": res["lanes"],
+        "batch_over_loop": f["over_per_job_loop"],
+        "identical_to_per_job": f["identical_to_per_job"] and res["lanes"]["identical_to_per_job"],
+        "autotune_picks": picks,
     }
 
 
@@ -401,14 +451,21 @@ def run_c4(a):
     }
 
 
-def _server_fpb(job, elem_bytes=8, cap=1 << 30):
-    """Frames per block the server gives a request: the library default, with
-    the request's staged spectra capped at 1 GiB (at least 16 frames)."""
+def _shared_fpb(job, T, cap, min_frames, elem_bytes=8):
+    """The library's block size for a job sharing the device (a batch, a served
+    request): T, with the staged spectra capped at `cap` bytes but never fewer
+    than 16 (M + 1) frames (its FP64 accumulator traffic per block) nor
+    min_frames."""
     per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
-    T = _default_fpb(job, elem_bytes)
-    if T * per_frame > cap:
-        T = max(16, cap // per_frame)
-    return int(T)
+    if T * per_frame <= cap:
+        return int(T)
+    t = max(cap // per_frame, min(T, 16 * (job.M + 1)), min_frames)
+    return int(min(t, T))
+
+
+def _server_fpb(job, elem_bytes=8):
+    """Frames per block the server gives a request (1 GiB cap, at least 16 frames)."""
+    return _shared_fpb(job, _default_fpb(job, elem_bytes), 1 << 30, 16, elem_bytes)
 
 
 def run_c5(a):
@@ -505,6 +562,52 @@ def run_c5(a):
         "completed": st["completed"], "failed": st["failed"],
         "all_ok": all(rc == 0 for rc in rcs),
     }
+
+
+def run_xcross(a):
+    """X stage on the vector ALUs (FP32) against MFMA (FP16, e4m3) as the
+    number of inputs per subband grows: C4-shaped jobs (4 x 32 MHz subbands,
+    4096 channels, 1024 frames) with M = 4 .. 32 stations, X-stage kernel time
+    per job from HIP events."""
+    import torch
+    from paper_1502_06894_amd import xcorr
+    from synth import configs
+    corr = xcorr.Correlator(0)
+    rows = []
+    for M in (4, 8, 16, 24, 32):
+        job = configs.c4_job(device="cuda", n_stations=M, n_frames=1024)
+        xcorr.job_to_device(job, "cuda:0")
+        row = {"inputs": M}
+        for prec in ("fp32", "fp16", "fp8"):
+            p = xcorr.PRECISIONS[prec]
+            ws = corr.alloc_workspace(job, precision=p)
+            out = corr.alloc_output(job)
+            for _ in range(a.warmup):
+                corr.correlate(job, precision=p, out=out, workspace=ws)
+            torch.cuda.synchronize()
+            corr.profile_begin(a.steps * 64 + 64)
+            for _ in range(a.steps):
+                corr.correlate(job, precision=p, out=out, workspace=ws)
+            torch.cuda.synchronize()
+            prof = corr.profile_end()
+            kind = "xmac" if prec == "fp32" else "xmfma"
+            ms = prof[kind][0] / a.steps
+            eb = {"fp32": 8, "fp16": 4, "fp8": 2}[prec]
+            gb = job.n_subbands * job.n_frames * job.M * job.n_chan * eb / 1e9
+            row[prec] = {"x_ms": round(ms, 4), "spectra_gb_per_s": round(gb / (ms * 1e-3), 1),
+                         "f_ms": round(prof["fstage"][0] / a.steps, 4)}
+            del ws, out
+        rows.append(row)
+        log(f"M = {M:2d}: X stage FP32 {row['fp32']['x_ms']:.3f} ms, FP16 {row['fp16']['x_ms']:.3f} ms, "
+            f"e4m3 {row['fp8']['x_ms']:.3f} ms")
+        del job
+        torch.cuda.synchronize()
+    return {"metric": "X-stage time per job (ms), vector FP32 vs MFMA", "value": None,
+            "unit": "ms", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "higher_is_better": False, "data": "synthetic",
+            "config": {"workload": "C4-shaped jobs: 4 x 32 MHz subbands, 4096 channels, "
+                                   "1024 frames, M = 4..32 single-pol stations"},
+            "rows": rows}
 
 
 def run_fringe(a):
@@ -662,6 +765,8 @@ def main():
     ap.add_argument("--rate-correct", action="store_true",
                     help="c1/c2: correct the space station's delay drift inside frames")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--calibrate-read", action="store_true",
+                    help="time a 4 GiB float32 sum (the device's streaming-read rate)")
     ap.add_argument("--rocpd-summary", metavar="DB", help="summarise a rocprofv3 database and exit")
     ap.add_argument("--traffic-json", nargs=4,
                     metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
@@ -673,6 +778,7 @@ def main():
     ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
                     help="c4: precision reported as the value")
     ap.add_argument("--jobs", type=int, default=64, help="c3: number of jobs")
+    ap.add_argument("--no-autotune", action="store_true", help="c3: library default tile shapes")
     ap.add_argument("--lanes", type=int, default=0,
                     help="c3: concurrent lanes (default 8); c5: server slots (default 16)")
     ap.add_argument("--requests", type=int, default=2000, help="c5: requests in the trace")
@@ -701,10 +807,13 @@ def main():
     if a.calibrate_copy:
         calibrate_copy()
         return
+    if a.calibrate_read:
+        calibrate_read()
+        return
 
-    if a.workload in ("c3", "c4", "c5", "fringe", "feed"):
+    if a.workload in ("c3", "c4", "c5", "fringe", "feed", "xcross"):
         res = {"c3": run_c3, "c4": run_c4, "c5": run_c5, "fringe": run_fringe,
-               "feed": run_feed}[a.workload](a)
+               "feed": run_feed, "xcross": run_xcross}[a.workload](a)
         print(json.dumps(res), flush=True)
         return
 

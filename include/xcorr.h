@@ -242,12 +242,26 @@ int xc_set_tuning(xc_ctx* ctx, const xc_tuning* t);
 int xc_get_tuning(const xc_ctx* ctx, xc_tuning* t);
 
 /* ---------------------------------------------------------------- batches */
-/* A batch runs many sub-integrations of uneven shapes as one unit: jobs are
- * spread longest-first over n_lanes concurrent HIP streams ("lanes"), each
- * lane with its own workspace arena, so small jobs overlap on the device and
- * the GPU stays full; results are identical to running each job alone.  With
- * XC_BATCH_GRAPH the launches are captured once as a hipGraph and a later call
- * with an identical batch replays the graph (one launch). */
+/* A batch runs many sub-integrations of uneven shapes as one unit (the
+ * batching of many sub-integrations in one persistent launch; abstract and
+ * section 2 describe the correlator whose sub-integrations these are).
+ * Default executor: short jobs (at most 4 blocks of frames_per_block frames)
+ * of one FFT length form a group that runs in rounds; round r takes block r of
+ * every job of the group and runs all of them as one delay launch, one
+ * F-stage launch that is persistent over the tasks of every job's block, and
+ * one X-stage launch per input-tile shape.  Groups of different FFT lengths run side by side on
+ * n_lanes concurrent HIP streams ("lanes"); one ingest (each distinct
+ * recording once), one clear of all accumulators and one finalise serve the
+ * whole batch.  Long jobs (their own launches fill the GPU) and jobs the
+ * fused kernels do not take (FP16 / FP8 precision, 16384 channels, drift
+ * correction, or an X-stage tuning other than the default) run as single jobs
+ * on the lanes, longest first.  XC_BATCH_LANES instead runs every
+ * job as a single job, spread longest-first over the lanes.  Either way the
+ * results are identical bit for bit to running each job alone with the
+ * batch's block size (the library default, capped so that a job's staged
+ * spectra stay within 1 GiB).  With XC_BATCH_GRAPH the launches are captured
+ * once as a hipGraph and a later call with an identical batch replays the
+ * graph (one launch). */
 typedef struct {
   xc_setup setup;
   const xc_station* st;        /* host [setup.n_stations] */
@@ -255,10 +269,11 @@ typedef struct {
 } xc_job;
 
 #define XC_BATCH_GRAPH 1
+#define XC_BATCH_LANES 2
 
-/* Device workspace a batch needs (0 if a job is invalid). */
+/* Device workspace a batch needs with these flags (0 if a job is invalid). */
 size_t xc_batch_workspace_bytes(xc_ctx* ctx, const xc_job* jobs, int32_t n_jobs,
-                                int32_t n_lanes);
+                                int32_t n_lanes, int32_t flags);
 /* Correlate jobs[0..n_jobs) (1 <= n_lanes <= 16).  Async on `stream`: all
  * results are complete when the stream reaches this point.  Error codes as
  * for xc_correlate_subint; the message names the failing job. */
@@ -311,7 +326,10 @@ void xc_server_destroy(xc_server* srv);
  * every job of the same shape (FFT length, inputs, subbands, recorded
  * streams, precision) on this context.  Runs on `stream` and synchronises.
  * out/workspace as for xc_correlate_subint; candidates whose workspace does
- * not fit ws_bytes are skipped.  best (host) may be NULL. */
+ * not fit ws_bytes are skipped (frames per block: the library default, 512,
+ * 1024 and 2048, or, when not even 512 fit, the largest power of two from 256
+ * down to 16 that does).  The library default (the first candidate) stays
+ * unless another candidate is more than 3 % faster.  best (host) may be NULL. */
 int xc_autotune(xc_ctx* ctx, const xc_setup* setup, const xc_station* st, const xc_output* out,
                 void* workspace, size_t ws_bytes, void* stream, xc_tuning* best);
 

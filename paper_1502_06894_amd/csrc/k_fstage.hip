@@ -103,6 +103,214 @@ __device__ inline void load_window(const DevJob& J, int s, const DelayRec& r, in
   }
 }
 
+// Compile-time shape of the F stage's tasks for variant W (see k_fstage).
+template <int N, int W>
+struct FTask {
+  using Gm = FGeom<N, fstage_twm<N, W>()>;
+  static constexpr int T = Gm::T, E = Gm::E, G = Gm::G;
+  // last-pass butterflies per thread: the thread's bins are t + b T + r N/16
+  // (b < BL, r < 16), the kept half r < 8
+  static constexpr int BL = E / 16;
+  static constexpr int kAnchor = E / 2 < 8 ? E / 2 : 8;   // exact phasor every kAnchor samples
+  // W = 2: a subband's pols share one set of fringe phasors (both see the same
+  // fringe phase), held in registers from the first pol to the second
+  static constexpr bool kShare = W == 2 || W == kFstageShare;
+  // W = kFstageRatePass: the drift-correction pass over the stations that ask
+  // for it: the window is weighted by the ramp (n - N/2) before the transform,
+  // and the stored spectrum Y (from the regular pass) becomes
+  // (1 - rho) Y + (2 pi i rho k / N) fd Yr.  Its tasks are (flagged station,
+  // frame group, input), finer than the regular (station, frame group), so
+  // that the few flagged stations still spread evenly over the workgroups.
+  static constexpr bool kRamp = W == kFstageRatePass;
+  // W = kFstageLean: tasks (station, frame group, group of up to kLeanGroup
+  // inputs); the group's codes are packed before the transforms, the words are
+  // loaded per task (no prefetch) and the fractional-delay phasors are stepped
+  // at the store instead of held in registers.  Asks for 4 waves per SIMD.
+  static constexpr bool kLean = W == kFstageLean;
+  // The next task's words are loaded while this task is transformed, except
+  // for N = 16384 (1024 threads, 128 registers each: no room for them).
+  static constexpr bool kPrefetch = N <= 8192 && !kLean && W != kFstageShare;
+  // the fractional-delay phasors are stepped at the store instead of held
+  static constexpr bool kFdStep = kLean || W == kFstageShare;
+};
+
+// Tasks per (station, frame group) of a job: one, or one per input (the
+// drift-correction pass), or one per group of up to kLeanGroup inputs.
+template <int N, int W>
+__device__ __forceinline__ int fstage_igroups(const DevJob& J) {
+  using F = FTask<N, W>;
+  return F::kRamp ? J.n_inputs : F::kLean ? (J.n_inputs + kLeanGroup - 1) / kLeanGroup : 1;
+}
+
+// One F-stage task of a frame slot: for every input of the task, the fringe
+// rotation of the window's samples (level lookups from `lut`), the FFT through
+// `lds`, the fractional-delay correction and the spectrum store.  The window's
+// payload words `wv` (field offset sh0) are loaded by the caller.  P, M, n_chan
+// and n_sb are J's.
+template <int N, int W, int OUT>
+__device__ __forceinline__ void fstage_task(
+    const DevJob& J, int P, int M, int n_chan, int n_sb, const PhaseRec* __restrict__ prec,
+    void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf, int s, int fl,
+    int in_t, const DelayRec& r, const uint32_t (&wv)[FTask<N, W>::E], int sh0, float2* lds,
+    const float* lut, const float2* tw_tab, int t) {
+  using F = FTask<N, W>;
+  using Gm = typename F::Gm;
+  constexpr int T = F::T, E = F::E, BL = F::BL, kAnchor = F::kAnchor;
+  constexpr bool kShare = F::kShare, kRamp = F::kRamp, kLean = F::kLean, kFdStep = F::kFdStep;
+  const double nc0 = (double)(t - N / 2);     // centred index of the thread's first sample
+  constexpr double TD = (double)T;
+  const bool in_blk = fl < nf;
+  const bool valid = r.valid != 0;
+  const float* lut_t = lut + (valid ? 0 : 4);
+  // fractional-delay phasors of this thread's kept output bins
+  // k = t + b T + r N/16 (b < BL, r < 8): exp(2 pi i k d / N) =
+  // exp(2 pi i (t + b T) d / N) * exp(2 pi i d / 16)^r
+  constexpr int FDK = kFdStep ? 1 : 8;
+  float2 fd[BL][FDK];
+  float2 fd_st;
+  {
+    const float dd = (float)r.d;
+    fd_st = phasor_turns(dd * (1.0f / 16.0f));
+#pragma unroll
+    for (int b = 0; b < BL; ++b) {
+      fd[b][0] = phasor_turns((float)(t + b * T) * dd * (1.0f / (float)N));
+#pragma unroll
+      for (int rr = 1; rr < FDK; ++rr) fd[b][rr] = cmul(fd[b][rr - 1], fd_st);
+    }
+  }
+
+  // the fringe phasors of a subband, kept for its second pol when kShare
+  float2 zs[E];
+  // (a drift-correction task is one input, a lean task a group of inputs)
+  const int in_lo = kRamp ? in_t : kLean ? in_t * kLeanGroup : 0;
+  const int in_hi = kRamp ? in_t + 1
+                          : kLean ? min(in_lo + kLeanGroup, J.n_inputs) : J.n_inputs;
+  // lean: the group's 2-bit codes, 16 per input packed in one register, so
+  // that the window words are not held across the transforms
+  uint32_t codes[kLean ? kLeanGroup : 1];
+  if constexpr (kLean) {
+#pragma unroll
+    for (int i = 0; i < kLeanGroup; ++i) {
+      const int sh = sh0 + 2 * J.stream_map[min(in_lo + i, in_hi - 1)];
+      uint32_t c = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) c |= ((wv[e] >> sh) & 3u) << (2 * e);
+      codes[i] = c;
+    }
+  }
+  for (int in = in_lo; in < in_hi; ++in) {
+    const int sb = in / P, p = in - sb * P;
+    const int sh = sh0 + 2 * J.stream_map[in];
+    uint32_t code_in = 0;
+    if constexpr (kLean) {
+      const int i = in - in_lo;
+      code_in = codes[0];
+#pragma unroll
+      for (int j = 1; j < kLeanGroup; ++j) code_in = i == j ? codes[j] : code_in;
+    }
+    if (!kShare || p == 0) {
+      PhaseRec ph;
+      if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
+      else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
+      // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
+      // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
+      // rho: its constant change 2 phi2 T^2), restarted exactly every kAnchor samples.
+      // Keeping w fixed leaves out phi2 T^2 e (e - 1) turns at the e-th sample
+      // after an anchor; where that stays below 1e-8 turns across all E of a
+      // thread's samples (ground stations, a spacecraft away from perigee) one
+      // anchor and the first-order recurrence serve them all (4 fewer
+      // operations per sample, one anchor instead of E / kAnchor).  The test
+      // is per (station, subband, frame), hence uniform across the wave.
+      const bool quad = fabs(ph.phi2) * TD * TD * (double)(E * (E - 1)) > 1e-8;
+      float2 w = make_float2(1.f, 0.f);
+      if (quad) {
+        const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (e % kAnchor == 0) {
+            const double nc = nc0 + (double)e * TD;
+            zs[e] = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
+            w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
+          } else {
+            zs[e] = cmul(zs[e - 1], w);
+            w = cmul(w, rho);
+          }
+        }
+      } else {
+        zs[0] = phasor_turns(frac_f(fma(fma(ph.phi2, nc0, ph.phi1), nc0, ph.phi0)));
+        w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc0 + TD)));
+#pragma unroll
+        for (int e = 1; e < E; ++e) zs[e] = cmul(zs[e - 1], w);
+      }
+    }
+    float2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      float q = kLean ? lut_t[(code_in >> (2 * e)) & 3u] : lut_t[(wv[e] >> sh) & 3u];
+      if constexpr (kRamp) q *= (float)(t + e * T - N / 2);
+      v[e] = make_float2(q * zs[e].x, q * zs[e].y);
+    }
+    if constexpr (Gm::tw_mode == kTwFull) {
+      fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
+    } else {
+      fft_forward<N>(v, lds, TwSplit<N>{tw_tab}, t);
+    }
+    if (in_blk) {
+      const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+      const int8_t* ex = OUT == kOutF32 ? nullptr
+                                        : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
+#pragma unroll
+      for (int b = 0; b < BL; ++b) {
+        float2 fdr = fd[b][0];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+          const int k = t + b * T + rr * (N / 16);
+          if constexpr (kFdStep) {
+            if (rr > 0) fdr = cmul(fdr, fd_st);
+          } else {
+            fdr = fd[b][rr];
+          }
+          if constexpr (kRamp) {
+            float2* sp = static_cast<float2*>(spec) + row + k;
+            if (valid) {
+              const float2 old = *sp;
+              const float2 yr = cmul(v[b + rr * BL], fdr);
+              const float rho = r.rate, a = 6.28318530717958648f * rho * (float)k / (float)N;
+              *sp = make_float2((1.0f - rho) * old.x - a * yr.y, (1.0f - rho) * old.y + a * yr.x);
+            }
+          } else {
+            const float2 y = valid ? cmul(v[b + rr * BL], fdr) : make_float2(0.f, 0.f);
+            put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+          }
+        }
+      }
+    }
+    __syncthreads();   // the next input reuses lds
+  }
+}
+
+// Per-workgroup set-up of the F stage: the 2-bit level table (offset binary:
+// -3.3359, -1, +1, +3.3359, then four zeros that an invalid frame's lookups
+// are pointed at) and the twiddle tables, in LDS after the G exchange buffers.
+template <int N, int W>
+__device__ __forceinline__ void fstage_setup(const float2* __restrict__ tw, float*& lut,
+                                             float2*& tw_tab) {
+  using Gm = typename FTask<N, W>::Gm;
+  extern __shared__ float2 lds_all[];
+  unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds_all);
+  lut = reinterpret_cast<float*>(lds_b + Gm::lut_off);
+  if (threadIdx.x < 8) {
+    const float lv[4] = {-3.3359f, -1.0f, 1.0f, 3.3359f};
+    lut[threadIdx.x] = threadIdx.x < 4 ? lv[threadIdx.x] : 0.0f;
+  }
+  tw_tab = reinterpret_cast<float2*>(lds_b + Gm::tw_off);
+  if constexpr (Gm::tw_mode == kTwFull)
+    tw_lds_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
+  else
+    tw_split_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
+  __syncthreads();
+}
+
 // A workgroup holds G frame slots of T threads and works through tasks
 // (station, group of G frames): first task blockIdx.x, then gridDim.x + the
 // next value of the shared counter *ctr (zero at launch), so workgroups that
@@ -122,30 +330,12 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
              const PhaseRec* __restrict__ prec, const float2* __restrict__ tw,
              void* __restrict__ spec, const int8_t* __restrict__ scale_exp, int nf,
              unsigned* __restrict__ ctr) {
-  using Gm = FGeom<N, fstage_twm<N, W>()>;
-  constexpr int T = Gm::T, E = Gm::E, G = Gm::G;
-  __shared__ int next_task;
-  // last-pass butterflies per thread: the thread's bins are t + b T + r N/16
-  // (b < BL, r < 16), the kept half r < 8
-  constexpr int BL = E / 16;
-  constexpr int kAnchor = E / 2 < 8 ? E / 2 : 8;   // exact phasor every kAnchor samples
-  // W = 2: a subband's pols share one set of fringe phasors (both see the same
-  // fringe phase), held in registers from the first pol to the second
-  constexpr bool kShare = W == 2 || W == kFstageShare;
-  // W = kFstageRatePass: the drift-correction pass over the stations that ask
-  // for it: the window is weighted by the ramp (n - N/2) before the transform,
-  // and the stored spectrum Y (from the regular pass) becomes
-  // (1 - rho) Y + (2 pi i rho k / N) fd Yr.  Its tasks are (flagged station,
-  // frame group, input), finer than the regular (station, frame group), so
-  // that the few flagged stations still spread evenly over the workgroups.
-  constexpr bool kRamp = W == kFstageRatePass;
-  // W = kFstageLean: tasks (station, frame group, group of up to kLeanGroup
-  // inputs); the group's codes are packed before the transforms, the words are
-  // loaded per task (no prefetch) and the fractional-delay phasors are stepped
-  // at the store instead of held in registers.  Asks for 4 waves per SIMD.
-  constexpr bool kLean = W == kFstageLean;
+  using F = FTask<N, W>;
+  constexpr int T = F::T, E = F::E, G = F::G;
+  constexpr bool kRamp = F::kRamp, kLean = F::kLean, kPrefetch = F::kPrefetch;
   static_assert(!kRamp || OUT == kOutF32, "the drift correction rewrites FP32 spectra");
   static_assert(!kLean || 2 * E <= 32, "a lean input's codes fit one 32-bit register");
+  __shared__ int next_task;
   extern __shared__ float2 lds_all[];
   const DevJob& J = *job;
   const int g = threadIdx.x / T, t = threadIdx.x % T;
@@ -156,26 +346,14 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     n_flag = 0;
     for (int i = 0; i < J.n_stations; ++i) n_flag += J.st[i].rate_correct ? 1 : 0;
   }
-  const int n_igroups = kRamp ? J.n_inputs
-                              : kLean ? (J.n_inputs + kLeanGroup - 1) / kLeanGroup : 1;
+  const int n_igroups = fstage_igroups<N, W>(J);
   const int per_station = n_groups * n_igroups;
   const int n_tasks = per_station * n_flag;
 
   float2* lds = lds_all + g * lds_words<N>();
-  // 2-bit code -> level (offset binary: -3.3359, -1, +1, +3.3359), and four
-  // zeros that an invalid frame's lookups are pointed at
-  unsigned char* lds_b = reinterpret_cast<unsigned char*>(lds_all);
-  float* lut = reinterpret_cast<float*>(lds_b + Gm::lut_off);
-  if (threadIdx.x < 8) {
-    const float lv[4] = {-3.3359f, -1.0f, 1.0f, 3.3359f};
-    lut[threadIdx.x] = threadIdx.x < 4 ? lv[threadIdx.x] : 0.0f;
-  }
-  float2* tw_tab = reinterpret_cast<float2*>(lds_b + Gm::tw_off);
-  if constexpr (Gm::tw_mode == kTwFull)
-    tw_lds_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
-  else
-    tw_split_fill<N>(tw_tab, tw, threadIdx.x, blockDim.x);
-  __syncthreads();
+  float* lut;
+  float2* tw_tab;
+  fstage_setup<N, W>(tw, lut, tw_tab);
 
   // With whole waves per frame (T >= 64) the frame index is wave-uniform: the
   // delay and phase records then come in through scalar loads, which a wave
@@ -228,12 +406,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
   uint32_t wv[E];
   int sh0;
   load_window<N>(J, s, r, t, wv, sh0);
-  const double nc0 = (double)(t - N / 2);     // centred index of the thread's first sample
-  constexpr double TD = (double)T;
 
-  // The next task's words are loaded while this task is transformed, except
-  // for N = 16384 (1024 threads, 128 registers each: no room for them).
-  constexpr bool kPrefetch = N <= 8192 && !kLean && W != kFstageShare;
   while (task < n_tasks) {
     if (threadIdx.x == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
     __syncthreads();
@@ -245,135 +418,9 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
     int sh0_n = 0;
     if constexpr (kPrefetch) load_window<N>(J, s_n, r_n, t, wv_n, sh0_n);
 
-    const bool in_blk = fl < nf;
-    const bool valid = r.valid != 0;
-    const float* lut_t = lut + (valid ? 0 : 4);
-    // fractional-delay phasors of this thread's kept output bins
-    // k = t + b T + r N/16 (b < BL, r < 8): exp(2 pi i k d / N) =
-    // exp(2 pi i (t + b T) d / N) * exp(2 pi i d / 16)^r
-    constexpr bool kFdStep = kLean || W == kFstageShare;
-    constexpr int FDK = kFdStep ? 1 : 8;
-    float2 fd[BL][FDK];
-    float2 fd_st;
-    {
-      const float dd = (float)r.d;
-      fd_st = phasor_turns(dd * (1.0f / 16.0f));
-#pragma unroll
-      for (int b = 0; b < BL; ++b) {
-        fd[b][0] = phasor_turns((float)(t + b * T) * dd * (1.0f / (float)N));
-#pragma unroll
-        for (int rr = 1; rr < FDK; ++rr) fd[b][rr] = cmul(fd[b][rr - 1], fd_st);
-      }
-    }
+    fstage_task<N, W, OUT>(J, P, M, n_chan, n_sb, prec, spec, scale_exp, nf, s, fl, in_t, r, wv,
+                           sh0, lds, lut, tw_tab, t);
 
-    // the fringe phasors of a subband, kept for its second pol when kShare
-    float2 zs[E];
-    // (a drift-correction task is one input, a lean task a group of inputs)
-    const int in_lo = kRamp ? in_t : kLean ? in_t * kLeanGroup : 0;
-    const int in_hi = kRamp ? in_t + 1
-                            : kLean ? min(in_lo + kLeanGroup, J.n_inputs) : J.n_inputs;
-    // lean: the group's 2-bit codes, 16 per input packed in one register, so
-    // that the window words are not held across the transforms
-    uint32_t codes[kLean ? kLeanGroup : 1];
-    if constexpr (kLean) {
-#pragma unroll
-      for (int i = 0; i < kLeanGroup; ++i) {
-        const int sh = sh0 + 2 * J.stream_map[min(in_lo + i, in_hi - 1)];
-        uint32_t c = 0;
-#pragma unroll
-        for (int e = 0; e < E; ++e) c |= ((wv[e] >> sh) & 3u) << (2 * e);
-        codes[i] = c;
-      }
-    }
-    for (int in = in_lo; in < in_hi; ++in) {
-      const int sb = in / P, p = in - sb * P;
-      const int sh = sh0 + 2 * J.stream_map[in];
-      uint32_t code_in = 0;
-      if constexpr (kLean) {
-        const int i = in - in_lo;
-        code_in = codes[0];
-#pragma unroll
-        for (int j = 1; j < kLeanGroup; ++j) code_in = i == j ? codes[j] : code_in;
-      }
-      if (!kShare || p == 0) {
-        PhaseRec ph;
-        if (in_blk) ph = prec[((size_t)s * n_sb + sb) * nf + fl];
-        else ph.phi0 = ph.phi1 = ph.phi2 = 0.0;
-        // fringe phasors z_e = exp(2 pi i phi(t + e T)) by the second-order recurrence
-        // z_{e+1} = z_e w_e, w_{e+1} = w_e rho (w_e: phase step to the next sample,
-        // rho: its constant change 2 phi2 T^2), restarted exactly every kAnchor samples.
-        // Keeping w fixed leaves out phi2 T^2 e (e - 1) turns at the e-th sample
-        // after an anchor; where that stays below 1e-8 turns across all E of a
-        // thread's samples (ground stations, a spacecraft away from perigee) one
-        // anchor and the first-order recurrence serve them all (4 fewer
-        // operations per sample, one anchor instead of E / kAnchor).  The test
-        // is per (station, subband, frame), hence uniform across the wave.
-        const bool quad = fabs(ph.phi2) * TD * TD * (double)(E * (E - 1)) > 1e-8;
-        float2 w = make_float2(1.f, 0.f);
-        if (quad) {
-          const float2 rho = phasor_turns(frac_f(2.0 * ph.phi2 * TD * TD));
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            if (e % kAnchor == 0) {
-              const double nc = nc0 + (double)e * TD;
-              zs[e] = phasor_turns(frac_f(fma(fma(ph.phi2, nc, ph.phi1), nc, ph.phi0)));
-              w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc + TD)));
-            } else {
-              zs[e] = cmul(zs[e - 1], w);
-              w = cmul(w, rho);
-            }
-          }
-        } else {
-          zs[0] = phasor_turns(frac_f(fma(fma(ph.phi2, nc0, ph.phi1), nc0, ph.phi0)));
-          w = phasor_turns(frac_f(ph.phi1 * TD + ph.phi2 * TD * (2.0 * nc0 + TD)));
-#pragma unroll
-          for (int e = 1; e < E; ++e) zs[e] = cmul(zs[e - 1], w);
-        }
-      }
-      float2 v[E];
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        float q = kLean ? lut_t[(code_in >> (2 * e)) & 3u] : lut_t[(wv[e] >> sh) & 3u];
-        if constexpr (kRamp) q *= (float)(t + e * T - N / 2);
-        v[e] = make_float2(q * zs[e].x, q * zs[e].y);
-      }
-      if constexpr (Gm::tw_mode == kTwFull) {
-        fft_forward<N>(v, lds, TwLds<N>{tw_tab}, t);
-      } else {
-        fft_forward<N>(v, lds, TwSplit<N>{tw_tab}, t);
-      }
-      if (in_blk) {
-        const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
-        const int8_t* ex = OUT == kOutF32 ? nullptr
-                                          : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
-#pragma unroll
-        for (int b = 0; b < BL; ++b) {
-          float2 fdr = fd[b][0];
-#pragma unroll
-          for (int rr = 0; rr < 8; ++rr) {
-            const int k = t + b * T + rr * (N / 16);
-            if constexpr (kFdStep) {
-              if (rr > 0) fdr = cmul(fdr, fd_st);
-            } else {
-              fdr = fd[b][rr];
-            }
-            if constexpr (kRamp) {
-              float2* sp = static_cast<float2*>(spec) + row + k;
-              if (valid) {
-                const float2 old = *sp;
-                const float2 yr = cmul(v[b + rr * BL], fdr);
-                const float rho = r.rate, a = 6.28318530717958648f * rho * (float)k / (float)N;
-                *sp = make_float2((1.0f - rho) * old.x - a * yr.y, (1.0f - rho) * old.y + a * yr.x);
-              }
-            } else {
-              const float2 y = valid ? cmul(v[b + rr * BL], fdr) : make_float2(0.f, 0.f);
-              put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
-            }
-          }
-        }
-      }
-      __syncthreads();   // the next input reuses lds
-    }
     task = task_n;
     s = s_n;
     fl = fl_n;
@@ -385,6 +432,122 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
       for (int e = 0; e < E; ++e) wv[e] = wv_n[e];
     } else {
       load_window<N>(J, s, r, t, wv, sh0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- fused batches
+// One F-stage launch over the blocks of many jobs of one FFT length (a round
+// of a fused batch): the tasks of item i (one job's block) are numbered from
+// items[i].task0, and a workgroup's next task may belong to any item.  Each
+// task runs exactly as in k_fstage (same variant, same arithmetic), so a job's
+// spectra do not depend on what else shares the launch.
+template <int N, int W>
+__global__ void __attribute__((amdgpu_flat_work_group_size(1, FGeom<N>::WG),
+                               amdgpu_waves_per_eu(W == kFstageLean ? 4 : 1)))
+    k_fstage_fused(const FusedItem* __restrict__ items_g, int n_items, int n_tasks,
+                   const float2* __restrict__ tw, unsigned* __restrict__ ctr) {
+  using F = FTask<N, W>;
+  constexpr int T = F::T, E = F::E, G = F::G;
+  constexpr bool kLean = F::kLean, kPrefetch = F::kPrefetch;
+  static_assert(W == 0 || W == kFstageLean || W == kFstageShare, "fused F-stage variants");
+  __shared__ int next_task;
+  extern __shared__ float2 lds_all[];
+  const FusedItemsK items = fused_const(items_g);
+  const int g = threadIdx.x / T, t = threadIdx.x % T;
+  float2* lds = lds_all + g * lds_words<N>();
+  float* lut;
+  float2* tw_tab;
+  fstage_setup<N, W>(tw, lut, tw_tab);
+  // item it's job descriptor (constant data)
+  auto job_of = [&](int it) -> const DevJob& { return *(const DevJob*)&items[it].jd; };
+
+  // task -> (item, station, frame, input group); beyond the tasks: item 0 with
+  // an empty, invalid record
+  auto locate = [&](int task, int& it, int& st, int& fl, int& in) {
+    if (task >= n_tasks) {
+      it = 0;
+      st = 0;
+      fl = items[0].nf;
+      in = 0;
+      return;
+    }
+    int lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].task0 <= task)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    it = lo;
+    const int nf = items[it].nf;
+    const int n_ig = fstage_igroups<N, W>(job_of(it));
+    const int per_station = ((nf + G - 1) / G) * n_ig;
+    const int local = task - items[it].task0;
+    st = local / per_station;
+    int grp = local - st * per_station;
+    in = 0;
+    if constexpr (kLean) {
+      in = grp % n_ig;
+      grp /= n_ig;
+    }
+    fl = grp * G + g;
+    if (T >= 64) fl = __builtin_amdgcn_readfirstlane(fl);
+  };
+  auto record_of = [&](int it, int st, int fl) {
+    DelayRec r;
+    const int nf = items[it].nf;
+    if (fl < nf) {
+      r = items[it].drec[(size_t)st * nf + fl];
+    } else {
+      r.valid = 0;
+      r.d = 0.0;
+      r.base = 0;
+    }
+    return r;
+  };
+
+  int task = blockIdx.x;
+  int it = 0, s = 0, fl = 0, in_t = 0;
+  locate(task, it, s, fl, in_t);
+  DelayRec r = record_of(it, s, fl);
+  uint32_t wv[E];
+  int sh0;
+  load_window<N>(job_of(it), s, r, t, wv, sh0);
+
+  while (task < n_tasks) {
+    if (threadIdx.x == 0) next_task = (int)gridDim.x + (int)atomicAdd(ctr, 1u);
+    __syncthreads();
+    // the same value in every thread: kept in scalar registers, so that the
+    // item lookup and the item's fields are scalar too
+    const int task_n = __builtin_amdgcn_readfirstlane(next_task);
+    int it_n = 0, s_n = 0, fl_n = 0, in_n = 0;
+    locate(task_n, it_n, s_n, fl_n, in_n);
+    const DelayRec r_n = record_of(it_n, s_n, fl_n);
+    uint32_t wv_n[kPrefetch ? E : 1];
+    int sh0_n = 0;
+    if constexpr (kPrefetch) load_window<N>(job_of(it_n), s_n, r_n, t, wv_n, sh0_n);
+
+    {
+      const DevJob& J = job_of(it);
+      fstage_task<N, W, kOutF32>(J, J.n_pols, J.M, J.n_chan, J.n_subbands, items[it].prec,
+                                 items[it].spec, nullptr, items[it].nf, s, fl, in_t, r, wv, sh0,
+                                 lds, lut, tw_tab, t);
+    }
+
+    task = task_n;
+    it = it_n;
+    s = s_n;
+    fl = fl_n;
+    in_t = in_n;
+    r = r_n;
+    if constexpr (kPrefetch) {
+      sh0 = sh0_n;
+#pragma unroll
+      for (int e = 0; e < E; ++e) wv[e] = wv_n[e];
+    } else {
+      load_window<N>(job_of(it), s, r, t, wv, sh0);
     }
   }
 }
@@ -813,6 +976,76 @@ static hipError_t launch_big(const DevJob* job, int n_stations, int n_inputs,
   else
     return hipErrorInvalidValue;   // FP32 spectra fold the frame instead (k_fhalf)
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fused batch launchers
+template <int N, int W>
+static hipError_t launch_fused_nw(const FusedItem* items, int n_items, int n_tasks,
+                                  const float2* tw, unsigned* ctr, hipStream_t s) {
+  using Gm = typename FTask<N, W>::Gm;
+  static std::atomic<int> resident[64];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  int res = resident[dev].load();
+  if (!res) {
+    e = hipFuncSetAttribute((const void*)k_fstage_fused<N, W>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)Gm::lds_bytes);
+    int per_cu = 0, n_cu = 0;
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fstage_fused<N, W>, Gm::WG,
+                                                       Gm::lds_bytes);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    res = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+    resident[dev].store(res);
+  }
+  if (n_tasks <= 0) return hipSuccess;
+  const int grid = n_tasks < res ? n_tasks : res;
+  hipLaunchKernelGGL((k_fstage_fused<N, W>), dim3(grid), dim3(Gm::WG), Gm::lds_bytes, s, items,
+                     n_items, n_tasks, tw, ctr);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t launch_fused_n(int waves, const FusedItem* items, int n_items, int n_tasks,
+                                 const float2* tw, unsigned* ctr, hipStream_t s) {
+  if (waves == kFstageLean)
+    return launch_fused_nw<N, kFstageLean>(items, n_items, n_tasks, tw, ctr, s);
+  if (waves == kFstageShare)
+    return launch_fused_nw<N, kFstageShare>(items, n_items, n_tasks, tw, ctr, s);
+  if (waves == 0 && N < kLeanMinN)
+    return launch_fused_nw<N, 0>(items, n_items, n_tasks, tw, ctr, s);
+  return hipErrorInvalidValue;
+}
+
+int fstage_fused_variant(int N, int n_pols, int n_chan) {
+  const int w = fstage_variant(0, n_pols, n_chan, kOutF32);
+  return w == 0 && N >= kLeanMinN ? kFstageLean : w;
+}
+
+static_assert(FGeom<2048>::T == 2048 / 16 && FGeom<2048>::G == 2 && FGeom<8192>::G == 1,
+              "fstage_fused_tasks mirrors FGeom");
+
+int fstage_fused_tasks(int N, int waves, int n_stations, int n_inputs, int nf) {
+  const int T = N / 16;                   // threads per frame (FftPlan<N>: 16 values each)
+  const int G = T >= 256 ? 1 : 256 / T;   // frames per workgroup (FGeom<N>::G)
+  const int groups = (nf + G - 1) / G;
+  const int ig = waves == kFstageLean ? (n_inputs + kLeanGroup - 1) / kLeanGroup : 1;
+  return n_stations * groups * ig;
+}
+
+hipError_t launch_fstage_fused(int N, int waves, const FusedItem* items, int n_items,
+                               int n_tasks, const float2* tw, unsigned* ctr, hipStream_t s) {
+  switch (N) {
+#define XC_FFCASE(NN) \
+  case NN: return launch_fused_n<NN>(waves, items, n_items, n_tasks, tw, ctr, s);
+    XC_FFCASE(256) XC_FFCASE(512) XC_FFCASE(1024) XC_FFCASE(2048) XC_FFCASE(4096) XC_FFCASE(8192)
+    XC_FFCASE(16384)
+#undef XC_FFCASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 bool fstage_supported(int N) {

@@ -306,23 +306,46 @@ __device__ __forceinline__ void ring_mac(const float2 (&a)[kGroup], const float2
     }
 }
 
-template <int MP>
+// FUSED: one launch over the blocks of many jobs (a fused batch round) whose
+// inputs pad to the same MP: workgroup b belongs to the item whose xblk0 is
+// the last at or below b, and b - xblk0 enumerates that item's (channel tile,
+// subband, tile chunk x frame slice) as blockIdx (x, y, z) does otherwise.
+template <int MP, bool FUSED>
 __global__ void __launch_bounds__(1024)
     k_xmac_ring(const DevJob* __restrict__ job, const float2* __restrict__ spec,
                 double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
-                int frames_per_split, size_t slot_stride) {
+                int frames_per_split, size_t slot_stride, const FusedItem* __restrict__ items,
+                int n_items) {
   static_assert(MP % kGroup == 0 && MP <= 32, "ring stages hold at most 32 inputs");
   static_assert(kRing == 8, "one LDS variable per stage");
   constexpr int KC = 64;
   constexpr int F4 = MP * KC / 2;     // float4 per stage
   __shared__ float4 r0[F4], r1[F4], r2[F4], r3[F4], r4[F4], r5[F4], r6[F4], r7[F4];
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if constexpr (FUSED) {
+    const int it = fused_find(items, n_items, (int)blockIdx.x,
+                              [](const FusedItem& I) { return I.xblk0; });
+    const FusedItem& I = items[it];
+    job = I.job;
+    spec = I.spec;
+    vacc = I.vacc;
+    nf = I.nf;
+    frames_per_split = I.fps;
+    slot_stride = I.slot_stride;
+    const int n_ct = job->n_chan / KC;
+    int local = (int)blockIdx.x - I.xblk0;
+    bx = local % n_ct;
+    local /= n_ct;
+    by = local % job->n_subbands;
+    bz = local / job->n_subbands;
+  }
   const DevJob& J = *job;
   const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
   constexpr int ng = MP / kGroup;
   constexpr int ntiles = ng * (ng + 1) / 2;
-  const int sb = blockIdx.y;
-  const int k0 = blockIdx.x * KC;
-  const int zc = blockIdx.z % zchunks, split = blockIdx.z / zchunks;
+  const int sb = by;
+  const int k0 = bx * KC;
+  const int zc = bz % zchunks, split = bz / zchunks;
   const int fa = split * frames_per_split;
   const int fz = min(nf, fa + frames_per_split);
   if (fa >= fz) return;   // whole workgroup
@@ -422,8 +445,8 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
   if (Mp > 32 || n_chan % 64 != 0) return hipErrorInvalidValue;
-  const int n_splits = (nf + fps_max - 1) / fps_max;
-  const int fps = (nf + n_splits - 1) / n_splits;
+  int n_splits, fps;
+  xmac_splits(nf, fps_max, n_splits, fps);
   int tiles_per_wg = tpw_req > 0 && tpw_req < 16 ? tpw_req : 16;
   if (tiles_per_wg > ntiles) tiles_per_wg = ntiles;
   const int zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
@@ -433,8 +456,8 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
   dim3 block(64 * waves);
 #define XMAC_RING(MPV)                                                                    \
   case MPV:                                                                               \
-    hipLaunchKernelGGL((k_xmac_ring<MPV>), grid, block, 0, s, job, spec, vacc, nf,     \
-                       tiles_per_wg, zchunks, fps, slot_stride);                          \
+    hipLaunchKernelGGL((k_xmac_ring<MPV, false>), grid, block, 0, s, job, spec, vacc, nf, \
+                       tiles_per_wg, zchunks, fps, slot_stride, nullptr, 0);              \
     break;
   switch (Mp) {
     XMAC_RING(4) XMAC_RING(8) XMAC_RING(12) XMAC_RING(16) XMAC_RING(20) XMAC_RING(24)
@@ -442,6 +465,53 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
     default: return hipErrorInvalidValue;
   }
 #undef XMAC_RING
+  return hipGetLastError();
+}
+
+// Ring-kernel launch shape of inputs padded to Mp: tiles per workgroup, tile
+// chunks and waves (the same for every job of that Mp).
+static void ring_shape(int Mp, int& tiles_per_wg, int& zchunks, int& waves) {
+  const int ng = Mp / kGroup;
+  const int ntiles = ng * (ng + 1) / 2;
+  tiles_per_wg = ntiles < 16 ? ntiles : 16;
+  zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
+  waves = tiles_per_wg > Mp / 2 ? tiles_per_wg : Mp / 2;
+}
+
+bool xmac_fused_ok(int M, int n_chan) {
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  return Mp <= 32 && n_chan % 64 == 0;
+}
+
+void xmac_splits(int nf, int fps_max, int& n_splits, int& fps) {
+  n_splits = (nf + fps_max - 1) / fps_max;
+  fps = (nf + n_splits - 1) / n_splits;
+}
+
+int xmac_fused_blocks(int M, int n_chan, int n_subbands, int n_splits) {
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  int tpw, zchunks, waves;
+  ring_shape(Mp, tpw, zchunks, waves);
+  return n_chan / 64 * n_subbands * zchunks * n_splits;
+}
+
+hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_blocks,
+                             hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  int tpw, zchunks, waves;
+  ring_shape(Mp, tpw, zchunks, waves);
+  const dim3 grid(n_blocks), block(64 * waves);
+#define XMAC_FUSED(MPV)                                                                   \
+  case MPV:                                                                               \
+    hipLaunchKernelGGL((k_xmac_ring<MPV, true>), grid, block, 0, s, nullptr, nullptr,     \
+                       nullptr, 0, tpw, zchunks, 0, 0, items, n_items);                   \
+    break;
+  switch (Mp) {
+    XMAC_FUSED(4) XMAC_FUSED(8) XMAC_FUSED(12) XMAC_FUSED(16) XMAC_FUSED(20) XMAC_FUSED(24)
+    XMAC_FUSED(28) XMAC_FUSED(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef XMAC_FUSED
   return hipGetLastError();
 }
 

@@ -246,15 +246,12 @@ int xc_server_submit(xc_server* s, const xc_job* job, uint64_t* ticket) {
   std::lock_guard<std::mutex> g(s->mu);
   r->tu = effective_tuning(s->ctx, &r->setup);
   r->L = layout_of(&r->setup, r->st.data(), r->tu);
-  {
-    // bound each request's staged spectra (1 GiB) so that several fit in the budget together
-    const xc_setup& q = r->setup;
-    const size_t per_frame =
-        (size_t)q.n_subbands * q.n_stations * q.n_pols * q.n_chan * out_elem_bytes(r->L.out);
-    const size_t cap = (size_t)1 << 30;
-    if ((size_t)r->L.T * per_frame > cap && q.frames_per_block == 0) {
-      int T = (int)(cap / per_frame);
-      r->setup.frames_per_block = T < 16 ? 16 : T;
+  if (r->setup.frames_per_block == 0) {
+    // bound each request's staged spectra (1 GiB, or 16 (M + 1) frames where
+    // that is more) so that several fit in the budget together
+    const int T = shared_block_frames(r->setup, r->L, (size_t)1 << 30, 16);
+    if (T != r->L.T) {
+      r->setup.frames_per_block = T;
       r->L = layout_of(&r->setup, r->st.data(), r->tu);
     }
   }

@@ -10,6 +10,52 @@
 
 namespace xc {
 
+// One job's block of frames in a round of a fused batch: a device table of
+// these drives one delay, one weight, one F-stage and one X-stage launch per
+// round over the blocks of many jobs (every job of the round has the same FFT
+// length; an X launch takes the items of one input-tile shape).  Each launch
+// numbers its workgroups (or the F stage its tasks) consecutively over the
+// items; the *0 fields give the first number of each item.
+struct FusedItem {
+  DevJob jd;               // the job's descriptor, by value (read as constant data)
+  const DevJob* job;       // the same descriptor in the workspace
+  DelayRec* drec;          // [S][nf]
+  PhaseRec* prec;          // [S][n_sb][nf]
+  float2* spec;            // [n_sb][nf][M][n_chan]
+  double2* vacc;           // the job's FP64 accumulator slots
+  double* wst;             // the job's station-pair weights [S][S]
+  size_t slot_stride;      // double2 elements per slot
+  int64_t f0;              // first frame of the block
+  int32_t nf;              // frames in the block
+  int32_t fps;             // X stage: frames per FP32 slice
+  int32_t task0;           // F stage: tasks before this item
+  int32_t dblk0;           // delay kernel: workgroups before this item
+  int32_t wblk0;           // weight kernel: workgroups before this item
+  int32_t xblk0;           // X stage: workgroups before this item in its launch
+};
+
+// The item whose numbers start at or before `x` (first[i] ascending, first[0] = 0).
+template <class Get>
+__device__ inline int fused_find(const FusedItem* items, int n, int x, Get first) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(items[mid]) <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int fused_item_of(const FusedItem* items, int n, int task) {
+  return fused_find(items, n, task, [](const FusedItem& I) { return I.task0; });
+}
+// The item table viewed as constant memory: the launches that read it never
+// write it, and through this view the compiler keeps the item's fields (and
+// its job's) in scalar registers, loaded with scalar loads.
+typedef const __attribute__((address_space(4))) FusedItem* FusedItemsK;
+__device__ inline FusedItemsK fused_const(const FusedItem* items) { return (FusedItemsK)items; }
+
 // A0: frame_ok[f] = sync word of recording frame f is good.
 hipError_t launch_ingest(const uint32_t* words, int64_t n_frames, uint8_t* frame_ok,
                          hipStream_t s);
@@ -95,6 +141,56 @@ hipError_t launch_weights(const DelayRec* drec, int n_stations, int nf, double* 
 hipError_t launch_finalise(const double2* vacc, int n_slots, size_t slot_stride,
                            const double* wst, int n_stations, int n_pols, float2* vis,
                            float* weight, int n_subbands, int M, int n_chan, hipStream_t s);
+// Fused batches (FP32 spectra, the regular F-stage variants 0, kFstageLean and
+// kFstageShare; no drift-correction pass).  `items` is a device table of
+// n_items FusedItem; ctr a zeroed counter (launch_delays_fused clears it).
+// Delay and phase records of every item's block (+ clears ctr[0], ctr[1]).
+hipError_t launch_delays_fused(const FusedItem* items, int n_items, int n_blocks, unsigned* ctr,
+                               hipStream_t s);
+// Workgroups launch_delays_fused needs for an item of nf frames, S stations, n_sb subbands.
+int delays_fused_blocks(int nf, int n_stations, int n_subbands);
+// Station-pair weights of every item's block, added to the item's job's wst.
+hipError_t launch_weights_fused(const FusedItem* items, int n_items, int n_blocks, hipStream_t s);
+int weights_fused_blocks(int nf, int n_stations);
+// F stage over every item's block (all items of FFT length N, variant `waves`).
+hipError_t launch_fstage_fused(int N, int waves, const FusedItem* items, int n_items,
+                               int n_tasks, const float2* tw, unsigned* ctr, hipStream_t s);
+// F-stage tasks of an item (job with S stations and n_inputs inputs, nf frames).
+int fstage_fused_tasks(int N, int waves, int n_stations, int n_inputs, int nf);
+// The F-stage variant of a fused batch item: what the per-job path would run.
+int fstage_fused_variant(int N, int n_pols, int n_chan);
+// X stage over every item (all with inputs padded to Mp = MP, 64-channel tiles:
+// the LDS-ring kernel); workgroups of one item: xmac_fused_blocks.
+hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_blocks,
+                             hipStream_t s);
+int xmac_fused_blocks(int M, int n_chan, int n_subbands, int n_splits);
+// Frame slices of a block of nf frames with at most fps_max frames each: their
+// number and the (balanced) frames per slice, as the X stage splits a block.
+void xmac_splits(int nf, int fps_max, int& n_splits, int& fps);
+// Whether the fused X stage takes a job of M inputs and n_chan channels.
+bool xmac_fused_ok(int M, int n_chan);
+
+// One job of a fused batch's finalise (blk0: workgroups before it).
+struct FusedOut {
+  const double2* vacc;
+  const double* wst;
+  float2* vis;
+  float* weight;
+  size_t slot_stride;
+  int32_t n_slots, S, P, M, nbl, n_chan, n_sb, blk0;
+};
+hipError_t launch_finalise_fused(const FusedOut* outs, int n_outs, int n_blocks, hipStream_t s);
+int finalise_fused_blocks(int n_subbands, int M, int n_chan);
+// One recording of a fused batch's ingest (blk0: workgroups before it).
+struct FusedMask {
+  const uint32_t* words;
+  uint8_t* ok;
+  int64_t n_frames;
+  int32_t blk0;
+};
+hipError_t launch_ingest_fused(const FusedMask* masks, int n_masks, int n_blocks, hipStream_t s);
+int ingest_fused_blocks(int64_t n_frames);
+
 // Test tap: unpacked levels of one (station, input, block frame).
 hipError_t launch_debug_unpack(const DevJob* job, const DelayRec* drec, int nf, int station,
                                int input, int fl, float* out, int N, hipStream_t s);

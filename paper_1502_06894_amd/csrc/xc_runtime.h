@@ -116,6 +116,14 @@ int validate(xc_ctx* c, const xc_setup* s, const xc_station* st);
 // holds two block buffers when the tuning allows it and there are two blocks.
 Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu,
                  bool overlap = false);
+// Frames per block of a job that shares the device with others (a batch, a
+// served request): its own block size L.T, with its staged spectra capped at
+// cap_bytes, but never fewer than kSlotAmortize (M + 1) frames (nor than
+// min_frames): the X stage reads and writes the job's FP64 accumulator, as
+// large as M + 1 frames of spectra, once per block, so at 16 (M + 1) frames
+// that traffic stays within 1/8 of the spectra's.  Returns L.T when it fits.
+constexpr int kSlotAmortize = 16;
+int shared_block_frames(const xc_setup& s, const Layout& L, size_t cap_bytes, int min_frames);
 // Descriptor for device address `dev_desc`; stations' frame_ok default to the arena masks.
 void build_desc(const xc_setup* s, const xc_station* st, const Layout& L,
                 const unsigned char* dev_desc, const unsigned char* arena, unsigned char* h);

@@ -209,6 +209,19 @@ Layout layout_of(const xc_setup* s, const xc_station* st, const xc_tuning& tu, b
   return L;
 }
 
+int shared_block_frames(const xc_setup& s, const Layout& L, size_t cap_bytes, int min_frames) {
+  const size_t per_frame =
+      (size_t)s.n_subbands * s.n_stations * s.n_pols * s.n_chan * out_elem_bytes(L.out);
+  if ((size_t)L.T * per_frame <= cap_bytes) return L.T;
+  int64_t T = (int64_t)(cap_bytes / per_frame);
+  const int64_t amortize = (int64_t)kSlotAmortize * (s.n_stations * s.n_pols + 1);
+  const int64_t floor_T = amortize < L.T ? amortize : L.T;
+  if (T < floor_T) T = floor_T;
+  if (T < min_frames) T = min_frames;
+  if (T > L.T) T = L.T;
+  return (int)T;
+}
+
 // Build the job descriptor for device address `dev` into host memory `h`.
 void build_desc(const xc_setup* s, const xc_station* st, const Layout& L,
                 const unsigned char* dev_desc, const unsigned char* arena, unsigned char* h) {

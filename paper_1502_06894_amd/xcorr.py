@@ -49,6 +49,7 @@ class XcJob(C.Structure):
 
 
 XC_BATCH_GRAPH = 1
+XC_BATCH_LANES = 2
 
 
 class XcTuning(C.Structure):
@@ -120,7 +121,8 @@ def load_library() -> C.CDLL:
                                           C.c_int32, C.c_int64, P, P, C.c_size_t, P]),
             "xc_debug_spectra": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
                                            C.c_int64, C.c_int32, P, P, C.c_size_t, P]),
-            "xc_batch_workspace_bytes": (C.c_size_t, [P, C.POINTER(XcJob), C.c_int32, C.c_int32]),
+            "xc_batch_workspace_bytes": (C.c_size_t, [P, C.POINTER(XcJob), C.c_int32, C.c_int32,
+                                                      C.c_int32]),
             "xc_correlate_batch": (C.c_int, [P, C.POINTER(XcJob), C.c_int32, C.c_int32, C.c_int32,
                                              P, C.c_size_t, P]),
             "xc_autotune": (C.c_int, [P, C.POINTER(XcSetup), C.POINTER(XcStation),
@@ -283,13 +285,16 @@ class Correlator:
         return ms, outs, arr
 
     def correlate_batch(self, jobs, *, n_lanes: int = 4, graph: bool = False,
-                        precision=XC_FP32, outs=None, workspace: Optional[torch.Tensor] = None,
-                        stream=None):
+                        lanes_only: bool = False, precision=XC_FP32, outs=None,
+                        workspace: Optional[torch.Tensor] = None, stream=None):
         """Correlate a list of jobs as one batch; returns [(vis, weight), ...].
 
+        Default: the fused executor (one persistent F-stage launch per FFT length
+        and round); lanes_only: every job as a single job on the lanes.
         precision: one value for all jobs, or a list with one per job."""
         if not isinstance(precision, (list, tuple)):
             precision = [precision] * len(jobs)
+        flags = (XC_BATCH_GRAPH if graph else 0) | (XC_BATCH_LANES if lanes_only else 0)
         ms = [_Marshal(j, p) for j, p in zip(jobs, precision)]
         if outs is None:
             outs = [self.alloc_output(j) for j in jobs]
@@ -298,27 +303,28 @@ class Correlator:
             arr[i] = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)),
                            XcOutput(vis.data_ptr(), w.data_ptr()))
         if workspace is None:
-            n = int(self.lib.xc_batch_workspace_bytes(self.ctx, arr, len(jobs), n_lanes))
+            n = int(self.lib.xc_batch_workspace_bytes(self.ctx, arr, len(jobs), n_lanes, flags))
             if n == 0:   # invalid job: the batch call itself reports which and why
-                self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, 0,
+                self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, flags,
                                                         None, 0, None))
             workspace = torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
-        self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes,
-                                                XC_BATCH_GRAPH if graph else 0,
+        self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, flags,
                                                 workspace.data_ptr(), workspace.numel(),
                                                 _stream_ptr(stream)))
         return outs
 
-    def batch_workspace(self, jobs, n_lanes: int = 4, precision=XC_FP32) -> torch.Tensor:
+    def batch_workspace(self, jobs, n_lanes: int = 4, precision=XC_FP32,
+                        lanes_only: bool = False) -> torch.Tensor:
         if not isinstance(precision, (list, tuple)):
             precision = [precision] * len(jobs)
+        flags = XC_BATCH_LANES if lanes_only else 0
         ms = [_Marshal(j, p) for j, p in zip(jobs, precision)]
         arr = (XcJob * len(jobs))()
         for i, m in enumerate(ms):
             arr[i] = XcJob(m.setup, C.cast(m.stations, C.POINTER(XcStation)), XcOutput(1, 1))
-        n = int(self.lib.xc_batch_workspace_bytes(self.ctx, arr, len(jobs), n_lanes))
+        n = int(self.lib.xc_batch_workspace_bytes(self.ctx, arr, len(jobs), n_lanes, flags))
         if n == 0:
-            self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, 0, None,
+            self._check(self.lib.xc_correlate_batch(self.ctx, arr, len(jobs), n_lanes, flags, None,
                                                     0, None))
         return torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
 

@@ -1,8 +1,11 @@
-"""GPU: batches (lanes, hipGraph capture/replay) and the autotuner.
+"""GPU: batches (the fused executor, lanes, hipGraph capture/replay) and the
+autotuner.
 
-A batch must reproduce each job's stand-alone result bit for bit (the same
-kernels and summation order run, only concurrently), for any lane count and
-on graph replay; a few jobs are also checked against the FP64 oracle.
+A batch must reproduce each job's stand-alone result bit for bit: the fused
+executor runs each job's blocks through the same arithmetic (one launch over
+the blocks of many jobs of one FFT length per round), the lane executor the
+same kernels concurrently; for any lane count and on graph replay.  A few jobs
+are also checked against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -54,11 +57,85 @@ def batch(xc, corr):
 
 def test_batch_matches_single_jobs_bitwise(xc, corr, batch):
     jobs, refs = batch
-    for lanes in (1, 3, 8):
-        outs = corr.correlate_batch(jobs, n_lanes=lanes)
-        torch.cuda.synchronize()
-        for (v, w), (rv, rw) in zip(outs, refs):
-            assert torch.equal(v, rv) and torch.equal(w, rw), lanes
+    for lanes_only in (False, True):
+        for lanes in (1, 3, 8):
+            outs = corr.correlate_batch(jobs, n_lanes=lanes, lanes_only=lanes_only)
+            torch.cuda.synchronize()
+            for (v, w), (rv, rw) in zip(outs, refs):
+                assert torch.equal(v, rv) and torch.equal(w, rw), (lanes_only, lanes)
+
+
+def _fused_mix(xc):
+    """Jobs for the fused executor's corner cases: several FFT lengths (the
+    lean F stage at 8192 and 16384 points), single and dual pol, input counts
+    of several tile shapes in one length, two jobs on the same recordings
+    (one mask each), a bad sync word and a recording cut short; plus jobs it
+    hands to single-job runs (16384 channels, FP16 precision, drift correction)."""
+    import dataclasses
+    rng = np.random.default_rng(404)
+    jobs, precs = [], []
+    for i, (S, nsb, P, n_chan, C, F) in enumerate([
+            (3, 2, 1, 256, 2, 300), (9, 1, 1, 256, 1, 140), (2, 3, 2, 256, 8, 200),
+            (5, 2, 1, 4096, 2, 40), (4, 5, 1, 8192, 8, 9), (3, 2, 1, 4096, 2, 70),
+            (6, 1, 2, 1024, 2, 90), (2, 1, 1, 16384, 1, 4), (3, 1, 1, 512, 1, 50)]):
+        jobs.append(configs.small_job(n_stations=S, n_subbands=nsb, n_pols=P, n_chan=n_chan, C=C,
+                                      n_frames=F, seed=500 + i, realistic=bool(i % 2)))
+        precs.append(xc.XC_FP32)
+    jobs[1].stations[2].frames = jobs[1].stations[2].frames.clone()
+    jobs[1].stations[2].frames[1, 0] = 0                      # bad sync word
+    jobs[5].stations[1].frames = jobs[5].stations[1].frames[:-2].contiguous()   # cut short
+    # a second job over job 1's recordings (the same tensors), a later stretch of time
+    jobs.append(dataclasses.replace(jobs[1], n_frames=100, sub_start=jobs[1].sub_start + 20 * 256))
+    precs.append(xc.XC_FP32)
+    # handed to single-job runs
+    jobs.append(configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=16384, C=1,
+                                  n_frames=3, seed=520))
+    precs.append(xc.XC_FP32)
+    jobs.append(configs.small_job(n_stations=4, n_subbands=2, n_pols=1, n_chan=256, C=2,
+                                  n_frames=60, seed=521))
+    precs.append(xc.XC_FP16_MFMA)
+    rc = configs.small_job(n_stations=2, n_subbands=1, n_pols=1, n_chan=1024, C=1, n_frames=20,
+                           seed=522)
+    rc = dataclasses.replace(rc, stations=[dataclasses.replace(rc.stations[0], rate_correct=True),
+                                           rc.stations[1]])
+    jobs.append(rc)
+    precs.append(xc.XC_FP32)
+    for j in jobs:
+        xc.job_to_device(j)
+    return jobs, precs
+
+
+@pytest.mark.parametrize("fpb", [0, 64])
+def test_fused_executor_corner_cases(xc, corr, fpb):
+    """The fused executor over the corner-case mix, in one block per job
+    (fpb = 0) and in 64-frame blocks (jobs of two to four blocks run in rounds,
+    job 0's five blocks make it a single job), with and without graph capture:
+    identical to each job run alone at the same block size; the FP32 jobs
+    within tolerance of the oracle."""
+    jobs, precs = _fused_mix(xc)
+    try:
+        corr.set_tuning(frames_per_block=fpb)
+        refs = [tuple(x.clone() for x in corr.correlate(j, precision=p))
+                for j, p in zip(jobs, precs)]
+        for graph in (False, True):
+            ws = corr.batch_workspace(jobs, n_lanes=3, precision=precs)
+            outs = [corr.alloc_output(j) for j in jobs]
+            for rep in range(2 if graph else 1):
+                for v, w in outs:
+                    v.zero_()
+                    w.zero_()
+                corr.correlate_batch(jobs, n_lanes=3, graph=graph, precision=precs, outs=outs,
+                                     workspace=ws)
+                torch.cuda.synchronize()
+                for k, ((v, w), (rv, rw)) in enumerate(zip(outs, refs)):
+                    assert torch.equal(v, rv) and torch.equal(w, rw), (fpb, graph, rep, k)
+    finally:
+        corr.set_tuning(frames_per_block=0)
+    if fpb == 64:
+        for k in (1, 4, 5, 9):
+            V, W = fx.correlate(jobs[k], threads=8)
+            assert np.array_equal(refs[k][1].cpu().numpy(), W.astype(np.float32)), k
+            assert rel_l2(refs[k][0].cpu().numpy(), V) < 1e-5, k
 
 
 def test_batch_against_oracle(xc, corr, batch):
@@ -113,7 +190,7 @@ def test_autotune_picks_a_candidate_and_stays_correct(xc, corr):
     V, W = fx.correlate(job, threads=8)
     xc.job_to_device(job)
     best = corr.autotune(job)
-    assert best["frames_per_block"] in (512, 1024, 2048)
-    assert best["xmac_frames_per_stage"] in (1, 2, 4, 8)
+    assert best["frames_per_block"] in (0, 512, 1024, 2048)       # 0: the library default
+    assert best["xmac_frames_per_stage"] in (0, 1, 2, 4, 8)
     vis, w = corr.correlate(job)           # uses the tuned shape
     assert rel_l2(vis.cpu().numpy(), V) < 1e-5
