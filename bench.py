@@ -87,6 +87,24 @@ def traffic_from_profile(kind: str, src_hash: str):
     return e.get("bytes_per_station_sample")
 
 
+# Vector-instruction issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-instructions/s
+# (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles).
+VALU_ISSUE_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def valu_from_profile(kind: str, src_hash: str):
+    """VALU instructions per station-sample and VALU busy of a kernel kind from
+    profiles/valu_counters.json (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU), or None."""
+    path = os.path.join(ROOT, "profiles", "valu_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        e = json.load(fh).get(kind)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e
+
+
 def roofline(kind: str, bytes_per_ss: float, flops_per_ss: float, src_files, prof_entry,
              ss_total: float) -> dict:
     """Roofline record of one kernel kind from its live HIP-event time.
@@ -112,6 +130,15 @@ def roofline(kind: str, bytes_per_ss: float, flops_per_ss: float, src_files, pro
            "frac_of_issue_ceiling": round(alg_flops / t_meas / 1e12 / FP32_ISSUE_CEILING_TFS, 4)}
     bound = "hbm" if t_hbm >= t_alu else "alu"
     main, side = (hbm, alu) if bound == "hbm" else (alu, hbm)
+    v = valu_from_profile(kind, src_hash)
+    valu = None
+    if v is not None:
+        rate = v["instr_per_station_sample"] * ss_launch / t_meas / 1e12
+        valu = {"instr_per_station_sample": round(v["instr_per_station_sample"], 2),
+                "achieved_tera_lane_instr_per_s": round(rate, 2),
+                "peak_at_2p4_ghz": round(VALU_ISSUE_PEAK_T, 2),
+                "frac": round(rate / VALU_ISSUE_PEAK_T, 4),
+                "valu_busy_counter": round(v["valu_busy"], 3)}
     return {"bound": bound, "achieved": main["achieved"], "peak": main["peak"],
             "unit": main["unit"], "frac": main["frac"],
             "traffic": None if tr is None else round(tr * ss_launch),
@@ -123,7 +150,8 @@ def roofline(kind: str, bytes_per_ss: float, flops_per_ss: float, src_files, pro
             "arithmetic_intensity_flop_per_byte": round(flops_per_ss / bytes_per_ss, 2),
             "ridge_flop_per_byte": round(FP32_PEAK_TFLOPS * 1e3 / HBM_PEAK_GBS, 2),
             "source_hash": src_hash,
-            ("alu" if bound == "hbm" else "hbm"): side}
+            ("alu" if bound == "hbm" else "hbm"): side,
+            "valu_issue": valu}
 
 
 def cpu_model() -> str:
@@ -246,6 +274,20 @@ def _counter_means(db_path: str, counter: str) -> dict:
         e[0] += 1
         e[1] += val
     return {k: tot / n for k, (n, tot) in agg.items()}
+
+
+def valu_json(db: str, ss_per_launch: float, kernels: dict) -> dict:
+    """VALU instructions per station-sample (SQ_INSTS_VALU x 64 / ss) and VALU
+    busy (SQ_ACTIVE_INST_VALU / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs)) per kernel kind."""
+    insts = _counter_means(db, "SQ_INSTS_VALU")
+    active = _counter_means(db, "SQ_ACTIVE_INST_VALU")
+    grbm = _counter_means(db, "GRBM_GUI_ACTIVE")
+    out = {"ss_per_launch": ss_per_launch}
+    for kind, (name, srcs) in kernels.items():
+        out[kind] = {"kernel": name, "source_hash": kernel_source_hash(srcs),
+                     "instr_per_station_sample": insts[name] * 64.0 / ss_per_launch,
+                     "valu_busy": active[name] / (256.0 * grbm[name] / 8.0)}
+    return out
 
 
 def traffic_json(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db: str,
@@ -772,6 +814,9 @@ def main():
                     metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"),
                     help="write profiles/hbm_counters.json from FETCH_SIZE / WRITE_SIZE runs of "
                          "the C2 workload and of --calibrate-copy, and exit")
+    ap.add_argument("--valu-json", metavar="VALU_DB",
+                    help="write profiles/valu_counters.json from an SQ_INSTS_VALU + "
+                         "SQ_ACTIVE_INST_VALU + GRBM_GUI_ACTIVE run of the C2 workload, and exit")
     ap.add_argument("--ss-per-launch", type=float, default=671088640.0,
                     help="--traffic-json: station-samples per F / X launch of the profiled run "
                          "(C2: 10 stations x 16 inputs x 2048 frames x 2048 samples)")
@@ -791,10 +836,18 @@ def main():
     if a.rocpd_summary:
         print(rocpd_summary(a.rocpd_summary))
         return
+    if a.valu_json:
+        d = valu_json(a.valu_json, a.ss_per_launch,
+                      {"fstage": ("xc::k_fstage<2048, 8, 0>", F_SOURCES),
+                       "xmac": ("xc::k_xmac_ring<20, false>", X_SOURCES)})
+        with open(os.path.join(ROOT, "profiles", "valu_counters.json"), "w") as fh:
+            json.dump(d, fh, indent=1)
+        print(json.dumps(d, indent=1))
+        return
     if a.traffic_json:
         d = traffic_json(*a.traffic_json, a.ss_per_launch,
                          {"fstage": ("xc::k_fstage<2048, 8, 0>", F_SOURCES),
-                          "xmac": ("xc::k_xmac_ring<20>", X_SOURCES)})
+                          "xmac": ("xc::k_xmac_ring<20, false>", X_SOURCES)})
         with open(os.path.join(ROOT, "profiles", "hbm_counters.json"), "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d, indent=1))
