@@ -382,7 +382,7 @@ def run_c3(a):
     picks = {}
     for t in tuned:
         key = (f"fpb {t.get('frames_per_block', 0)}, X stage "
-               f"{ {8: 'ring', 4: '4-frame stages', 2: '2-frame stages', 1: 'direct', 0: 'default'}[t.get('xmac_frames_per_stage', 0)] }"
+               f"{ {8: 'ring', 4: '4-frame stages', 3: 'matrix cores', 2: '2-frame stages', 1: 'direct', 0: 'default'}[t.get('xmac_frames_per_stage', 0)] }"
                + (f" {t['xmac_channels_per_wg']} ch" if t.get("xmac_channels_per_wg") else ""))
         picks[key] = picks.get(key, 0) + 1
     fpbs = [_batch_fpb(j, t.get("frames_per_block", 0)) for j, t in zip(jobs, tuned)]
@@ -451,13 +451,23 @@ def run_c3(a):
     }
 
 
+def _correlator(a):
+    """A library context with the --tune overrides (none: the library defaults)."""
+    from paper_1502_06894_amd import xcorr
+    corr = xcorr.Correlator(0)
+    if a.tune:
+        corr.set_tuning(**{k: int(v) for k, v in (kv.split("=", 1) for kv in a.tune)})
+        log(f"tuning: {corr.get_tuning()}")
+    return corr
+
+
 def run_c4(a):
     """32 stations, 4 x 32 MHz, 4096 channels, 1 s, FP32 / FP16 / FP8 X stage."""
     import torch
     from paper_1502_06894_amd import xcorr
     job, desc = make_job("c4")
     xcorr.job_to_device(job, "cuda:0")
-    corr = xcorr.Correlator(0)
+    corr = _correlator(a)
     res = {}
     for prec in ("fp32", "fp16", "fp8"):
         p = xcorr.PRECISIONS[prec]
@@ -607,7 +617,8 @@ def run_c5(a):
 
 
 def run_xcross(a):
-    """X stage on the vector ALUs (FP32) against MFMA (FP16, e4m3) as the
+    """X stage on the vector ALUs (FP32), on the matrix cores in FP32 (the same
+    fused multiply-adds, bit-identical sums) and on MFMA in FP16 / e4m3, as the
     number of inputs per subband grows: C4-shaped jobs (4 x 32 MHz subbands,
     4096 channels, 1024 frames) with M = 4 .. 32 stations, X-stage kernel time
     per job from HIP events."""
@@ -616,12 +627,18 @@ def run_xcross(a):
     from synth import configs
     corr = xcorr.Correlator(0)
     rows = []
-    for M in (4, 8, 16, 24, 32):
+    # (name, precision, X staging): FP32 on the vector ALUs through the LDS
+    # ring, FP32 on the matrix cores, FP16 / e4m3 on MFMA
+    variants = (("fp32", "fp32", 8), ("fp32m", "fp32", xcorr.XMAC_MATRIX), ("fp16", "fp16", 0),
+                ("fp8", "fp8", 0))
+    for M in (4, 8, 12, 16, 20, 24, 28, 32):
         job = configs.c4_job(device="cuda", n_stations=M, n_frames=1024)
         xcorr.job_to_device(job, "cuda:0")
         row = {"inputs": M}
-        for prec in ("fp32", "fp16", "fp8"):
+        vis32 = {}
+        for name, prec, xs in variants:
             p = xcorr.PRECISIONS[prec]
+            corr.set_tuning(xmac_frames_per_stage=xs)
             ws = corr.alloc_workspace(job, precision=p)
             out = corr.alloc_output(job)
             for _ in range(a.warmup):
@@ -632,19 +649,25 @@ def run_xcross(a):
                 corr.correlate(job, precision=p, out=out, workspace=ws)
             torch.cuda.synchronize()
             prof = corr.profile_end()
-            kind = "xmac" if prec == "fp32" else "xmfma"
+            kind = "xmfma" if prec != "fp32" else "xmac"
             ms = prof[kind][0] / a.steps
             eb = {"fp32": 8, "fp16": 4, "fp8": 2}[prec]
             gb = job.n_subbands * job.n_frames * job.M * job.n_chan * eb / 1e9
-            row[prec] = {"x_ms": round(ms, 4), "spectra_gb_per_s": round(gb / (ms * 1e-3), 1),
+            row[name] = {"x_ms": round(ms, 4), "spectra_gb_per_s": round(gb / (ms * 1e-3), 1),
                          "f_ms": round(prof["fstage"][0] / a.steps, 4)}
+            if prec == "fp32":
+                vis32[name] = out[0].clone()
             del ws, out
+        corr.set_tuning(xmac_frames_per_stage=0)
+        row["fp32m_bit_identical"] = bool(torch.equal(vis32["fp32"], vis32["fp32m"]))
         rows.append(row)
-        log(f"M = {M:2d}: X stage FP32 {row['fp32']['x_ms']:.3f} ms, FP16 {row['fp16']['x_ms']:.3f} ms, "
-            f"e4m3 {row['fp8']['x_ms']:.3f} ms")
-        del job
+        log(f"M = {M:2d}: X stage FP32 vector {row['fp32']['x_ms']:.3f} ms, matrix "
+            f"{row['fp32m']['x_ms']:.3f} ms (identical: {row['fp32m_bit_identical']}), "
+            f"FP16 {row['fp16']['x_ms']:.3f} ms, e4m3 {row['fp8']['x_ms']:.3f} ms")
+        del job, vis32
         torch.cuda.synchronize()
-    return {"metric": "X-stage time per job (ms), vector FP32 vs MFMA", "value": None,
+    return {"metric": "X-stage time per job (ms), vector FP32 vs matrix-core FP32 vs MFMA "
+                      "FP16/e4m3", "value": None,
             "unit": "ms", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
             "higher_is_better": False, "data": "synthetic",
             "config": {"workload": "C4-shaped jobs: 4 x 32 MHz subbands, 4096 channels, "
@@ -804,6 +827,8 @@ def main():
     ap.add_argument("--frames", type=int, default=0,
                     help="shorten the sub-integration (profiling runs only; not a bench figure)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="c2/c4: xc_tuning field override (repeatable)")
     ap.add_argument("--rate-correct", action="store_true",
                     help="c1/c2: correct the space station's delay drift inside frames")
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -887,7 +912,7 @@ def main():
     torch.cuda.synchronize()
     log(f"workload ready in {time.perf_counter() - t:.1f} s: {job.station_samples:.3e} "
         f"station-samples per step")
-    corr = xcorr.Correlator(0)
+    corr = _correlator(a)
     # every step runs the whole path, A0 included: the library checks each
     # recording frame's sync word (xc_ingest's kernel) inside the call
     ws = corr.alloc_workspace(job, frames_per_block=a.frames_per_block)

@@ -222,10 +222,17 @@ typedef struct {
   int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
                                       stages filled by direct memory-to-LDS loads (64-channel
                                       tiles, at most 32 inputs per subband; the default where
-                                      it applies); 2 or 4 = double-buffered stages of that many
+                                      it applies, except for 21-24 and 29-32 inputs per
+                                      subband, where 3 is); 2 or 4 = double-buffered stages of that many
                                       frames through registers (the default otherwise);
                                       1 = no LDS staging (inputs read from memory, one frame
-                                      ahead); 0 = default */
+                                      ahead); 3 = the FP32 products on the matrix cores
+                                      (v_mfma_f32_4x4x1: 16 channels per wave, inputs read
+                                      from memory a few frames ahead, at most 32 inputs per
+                                      subband, channels a multiple of 16); 0 = default.
+                                      Every staging gives bit-identical visibilities: the
+                                      matrix cores' products are fused multiply-adds with
+                                      one rounding, issued in the vector kernels' order */
   int32_t xmac_channels_per_wg;    /* X-stage channel tile: 0, 16, 32 or 64 */
   int32_t frames_per_block;        /* used when a setup says 0: 0 (= the library default)
                                       or 1..65536 */

@@ -29,6 +29,14 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-source additions.  k_xmac.hip: keep matrix-core accumulators in
+# ordinary VGPRs (left to its heuristics the compiler splits them between
+# VGPRs and AGPRs and copies them back and forth inside the frame loop).
+FILE_FLAGS = {
+    "k_xmac.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if c and os.path.exists(c):
@@ -52,7 +60,9 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     cc = hipcc()
     n = jobs or min(len(srcs), os.cpu_count() or 1, 16)
     with ThreadPoolExecutor(max_workers=n) as ex:
-        list(ex.map(lambda so: _run([cc, *HIPCC_FLAGS, "-c", so[0], "-o", so[1]], verbose),
+        list(ex.map(lambda so: _run([cc, *HIPCC_FLAGS,
+                                     *FILE_FLAGS.get(os.path.basename(so[0]), []),
+                                     "-c", so[0], "-o", so[1]], verbose),
                     zip(srcs, objs)))
     tmp = LIB + ".tmp"
     _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp], verbose)

@@ -515,6 +515,193 @@ hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_
   return hipGetLastError();
 }
 
+// Matrix-core variant: the same products on v_mfma_f32_4x4x1 (16 blocks of
+// 4 x 4 outer products per instruction).  A wave owns 16 channels of one
+// subband and one frame slice, and the 4 x 4 input tiles (gi <= gj) of one
+// part of the subband's tiles (all of them up to 24 inputs, else half, so
+// that the accumulators stay in registers at two waves per SIMD).
+// Block b of the instruction is lanes 4b .. 4b + 3 = channel c0 + b; the A
+// operand's row x and the B operand's column y of a block sit in lane 4b + x
+// and 4b + y, and register x of the result holds row x, column lane % 4.  So
+// lane 4b + r loads input 4g + r of every group g at its channel (four lanes
+// read 16 channels of one input: one 128-byte run), and that one register is
+// the A operand of the tiles in row g and the B operand of the tiles in
+// column g.  Each block element is a fused multiply-add into the accumulator
+// with one rounding, and the four real products of a complex one are issued
+// in the vector kernels' order, so the sums are bit-identical to theirs.
+// Operands come straight from memory, D frames ahead in registers (no LDS, no
+// barrier): the matrix cores do a tile's 64 FMAs in 4 instructions, and the
+// vector units only negate, address and load.
+template <int MG>
+struct MfmaTiles {
+  static constexpr int NT = MG * (MG + 1) / 2;
+  int gi[NT], gj[NT];
+  constexpr MfmaTiles() : gi(), gj() {
+    int t = 0;
+    for (int a = 0; a < MG; ++a)
+      for (int b = a; b < MG; ++b) {
+        gi[t] = a;
+        gj[t] = b;
+        ++t;
+      }
+  }
+};
+
+typedef float xm_f4 __attribute__((ext_vector_type(4)));
+
+// Tiles [PART * ceil(NT / S), ...) of MG groups over frames fa .. fz - 1,
+// added to the FP64 slot.  Tile indices are compile-time constants, so every
+// operand is a register.
+template <int MG, int S, int PART, int D>
+__device__ __forceinline__ void xmfma32_part(const float2* __restrict__ src,
+                                             const int (&roff)[MG], size_t fstride, int fa,
+                                             int fz, int M, int n_chan, int nbl, int sb, int c,
+                                             int r, double2* __restrict__ slot) {
+  constexpr MfmaTiles<MG> tiles{};
+  constexpr int NT = MfmaTiles<MG>::NT;
+  constexpr int NTW = (NT + S - 1) / S;
+  constexpr int T0 = PART * NTW;
+  constexpr int NTP = NT - T0 < NTW ? NT - T0 : NTW;   // tiles of this part
+  xm_f4 accr[NTP], acci[NTP];
+#pragma unroll
+  for (int t = 0; t < NTP; ++t) {
+    accr[t] = (xm_f4){0.f, 0.f, 0.f, 0.f};
+    acci[t] = (xm_f4){0.f, 0.f, 0.f, 0.f};
+  }
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  auto load = [&](int f, float2 (&x)[MG]) {
+    const f2v* p = reinterpret_cast<const f2v*>(src + (size_t)f * fstride);
+#pragma unroll
+    for (int g = 0; g < MG; ++g) {
+      // one reader per value: stream it past the caches; with several parts
+      // the block's other waves read it again, from cache
+      const f2v v = S == 1 ? __builtin_nontemporal_load(p + roff[g]) : p[roff[g]];
+      x[g] = make_float2(v.x, v.y);
+    }
+  };
+  auto mac = [&](const float2 (&x)[MG]) {
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) {
+      const float2 a = x[tiles.gi[T0 + t]], b = x[tiles.gj[T0 + t]];
+      // re: a.y b.y, then a.x b.x; im: -a.x b.y, then a.y b.x
+      accr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.y, accr[t], 0, 0, 0);
+      accr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.x, accr[t], 0, 0, 0);
+      acci[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.x, b.y, acci[t], 0, 0, 0);
+      acci[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.x, acci[t], 0, 0, 0);
+    }
+  };
+  // xb[d] holds frame f + d.  Whole rounds of D frames run without a branch,
+  // each register set reloaded (D frames ahead; past the slice, frame fz - 1
+  // again) as soon as its products are issued; the last fz - f < D frames
+  // are already in xb[0 ..] when the rounds end.
+  float2 xb[D][MG];
+#pragma unroll
+  for (int d = 0; d < D; ++d) load(min(fa + d, fz - 1), xb[d]);
+  int f = fa;
+  for (; f + D <= fz; f += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      mac(xb[d]);
+      load(min(f + d + D, fz - 1), xb[d]);
+      // keep the reload here: left to itself the scheduler sinks every load
+      // of the round below the last products, and the next round then waits
+      // for loads it has only just issued
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (f + d < fz) mac(xb[d]);
+#pragma unroll
+  for (int t = 0; t < NTP; ++t) {
+    const int gi = tiles.gi[T0 + t], gj = tiles.gj[T0 + t];
+#pragma unroll
+    for (int x = 0; x < kGroup; ++x) {
+      const int i = gi * kGroup + x, j = gj * kGroup + r;
+      if (i <= j && j < M) {
+        double2* o = slot + ((size_t)sb * nbl + bl_index(i, j, M)) * n_chan + c;
+        double2 v = *o;
+        v.x += (double)accr[t][x];
+        v.y += (double)acci[t][x];
+        *o = v;
+      }
+    }
+  }
+}
+
+// Workgroup: 4 / S channel blocks of 16 (fewer when the subband has fewer
+// channels), S waves (parts) per block.
+template <int MG, int S, int D>
+__global__ void __launch_bounds__(256)
+    k_xmac_mfma(const DevJob* __restrict__ job, const float2* __restrict__ spec,
+                double2* __restrict__ vacc, int nf, int frames_per_split, size_t slot_stride) {
+  const DevJob& J = *job;
+  const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int blocks = (int)(blockDim.x >> 6) / S;   // channel blocks per workgroup
+  const int r = lane & 3;
+  const int c = (blockIdx.x * blocks + wave / S) * 16 + (lane >> 2);
+  const int sb = blockIdx.y, split = blockIdx.z;
+  const int fa = split * frames_per_split;
+  const int fz = min(nf, fa + frames_per_split);
+  if (fa >= fz) return;
+  // this lane's rows 4g + r (rows past M repeat row M - 1: their products are
+  // never stored)
+  const float2* src = spec + (size_t)sb * nf * M * n_chan + c;
+  int roff[MG];
+#pragma unroll
+  for (int g = 0; g < MG; ++g) roff[g] = min(4 * g + r, M - 1) * n_chan;
+  const size_t fstride = (size_t)M * n_chan;
+  double2* slot = vacc + (size_t)split * slot_stride;
+  static_assert(S >= 1 && S <= 3, "one to three parts per channel block");
+  const int part = wave % S;
+  if (part == 0)
+    xmfma32_part<MG, S, 0, D>(src, roff, fstride, fa, fz, M, n_chan, nbl, sb, c, r, slot);
+  if constexpr (S >= 2)
+    if (part == 1)
+      xmfma32_part<MG, S, 1, D>(src, roff, fstride, fa, fz, M, n_chan, nbl, sb, c, r, slot);
+  if constexpr (S >= 3)
+    if (part == 2)
+      xmfma32_part<MG, S, 2, D>(src, roff, fstride, fa, fz, M, n_chan, nbl, sb, c, r, slot);
+}
+
+// Parts per channel block and frames in flight per wave for MG groups: the
+// accumulators (8 registers per tile) and D frames of operands (2 MG
+// registers each) within 256 VGPRs, two waves per SIMD.  Measured on
+// C4-shaped jobs (4096 channels, 1024 frames): splitting the tiles of 6 or 8
+// groups over more waves, each reading every input again from cache, is
+// slower (24 inputs 0.82 -> 1.20 ms, 32 inputs 1.70 -> 2.36 ms over three
+// parts), and more frames in flight gain at most 3 %.
+constexpr int mfma_parts(int MG) { return MG <= 6 ? 1 : 2; }
+constexpr int mfma_depth(int MG) { return MG <= 4 ? 8 : MG == 5 || MG == 7 ? 4 : 3; }
+
+static hipError_t launch_mfma(const DevJob* job, int M, int n_chan, int n_subbands,
+                              const float2* spec, double2* vacc, size_t slot_stride, int nf,
+                              int fps_max, hipStream_t s) {
+  const int ng = (M + kGroup - 1) / kGroup;
+  if (ng > 8 || n_chan % 16 != 0) return hipErrorInvalidValue;
+  int n_splits, fps;
+  xmac_splits(nf, fps_max, n_splits, fps);
+  const int S = mfma_parts(ng);
+  int blocks = 4 / S;   // channel blocks per workgroup
+  if (blocks > n_chan / 16) blocks = n_chan / 16;
+  dim3 grid(n_chan / (16 * blocks), n_subbands, n_splits);
+  dim3 block(64 * S * blocks);
+#define XMAC_MFMA(NG)                                                                     \
+  case NG:                                                                                \
+    hipLaunchKernelGGL((k_xmac_mfma<NG, mfma_parts(NG), mfma_depth(NG)>), grid, block, 0, s,\
+                       job, spec, vacc, nf, fps, slot_stride);                            \
+    break;
+  switch (ng) {
+    XMAC_MFMA(1) XMAC_MFMA(2) XMAC_MFMA(3) XMAC_MFMA(4) XMAC_MFMA(5) XMAC_MFMA(6)
+    XMAC_MFMA(7) XMAC_MFMA(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef XMAC_MFMA
+  return hipGetLastError();
+}
+
 static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subbands,
                                 const float2* spec, double2* vacc, size_t slot_stride, int nf,
                                 int fps_max, int kc_req, int tpw_req, hipStream_t s) {
@@ -624,8 +811,17 @@ hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
                        int fb, int kc, int tpw, hipStream_t s) {
   if (fps < 1) return hipErrorInvalidValue;
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  // default: the matrix cores where the vector ring would need two or three
+  // workgroups (each loading every input) per channel tile and the matrix
+  // cores measured faster (24 inputs: 0.82 vs 1.12 ms, 32: 1.70 vs 2.16 ms on
+  // C4-shaped jobs of 1024 frames; 28 inputs, where the matrix stage needs two
+  // waves per channel block, 1.47 vs 1.29 ms), else the ring
+  if (fb == 0 && (Mp == 24 || Mp == 32) && kc == 0 && tpw == 0 && n_chan % 16 == 0)
+    fb = kXmacMatrix;
   if ((fb == 0 || fb == kRing) && Mp <= 32 && (kc == 0 || kc == 64))
     return launch_ring(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, tpw, s);
+  if (fb == kXmacMatrix && Mp <= 32 && n_chan % 16 == 0)
+    return launch_mfma(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, s);
   if (fb == 1)
     return launch_direct(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, kc, tpw,
                          s);

@@ -128,8 +128,11 @@ hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_sub
 int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands);
 // A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
 // (double2), slot_stride elements apart; fps: xmac_frames_per_split of the job.
-// fb: staging (8 = LDS ring, 2 or 4 = register-staged stages, 1 = none, 0 = default);
-// kc: channel tile (16/32/64, 0 = auto); tpw: 4x4 tiles per workgroup (0 = all that fit).
+// fb: staging (8 = LDS ring, 2 or 4 = register-staged stages, 1 = none,
+// kXmacMatrix = FP32 products on the matrix cores, 0 = default); kc: channel
+// tile (16/32/64, 0 = auto); tpw: 4x4 tiles per workgroup (0 = all that fit).
+// Every staging gives bit-identical sums.
+constexpr int kXmacMatrix = 3;
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
                        const float2* spec, double2* vacc, size_t slot_stride, int nf, int fps,
                        int fb, int kc, int tpw, hipStream_t s);

@@ -50,6 +50,8 @@ class XcJob(C.Structure):
 
 XC_BATCH_GRAPH = 1
 XC_BATCH_LANES = 2
+# xc_tuning.xmac_frames_per_stage: FP32 products on the matrix cores
+XMAC_MATRIX = 3
 
 
 class XcTuning(C.Structure):

@@ -378,6 +378,45 @@ def test_block_overlap_bit_identical(xc, corr):
         corr.set_tuning(block_overlap=0)
 
 
+MATRIX_CASES = [
+    # name, small_job kwargs, frames_per_block: every input-group count 1..8
+    # (one and two tile parts per channel block), ragged frame counts and
+    # several slots
+    ("mg1", dict(n_stations=2, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=9), 0),
+    ("mg2", dict(n_stations=3, n_subbands=1, n_pols=2, n_chan=256, C=2, n_frames=23), 0),
+    ("mg3", dict(n_stations=6, n_subbands=2, n_pols=2, n_chan=128, C=4, n_frames=41), 0),
+    ("mg4", dict(n_stations=16, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=13), 0),
+    ("mg5_c2like", dict(n_stations=10, n_subbands=2, n_pols=2, n_chan=128, C=4, n_frames=37),
+     16),
+    ("mg6", dict(n_stations=23, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=30), 0),
+    ("mg7", dict(n_stations=14, n_subbands=1, n_pols=2, n_chan=128, C=2, n_frames=19), 0),
+    ("mg8_slots", dict(n_stations=32, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=700),
+     600),
+]
+
+
+@pytest.mark.parametrize("name,kw,fpb", MATRIX_CASES, ids=[c[0] for c in MATRIX_CASES])
+def test_matrix_core_x_stage(xc, corr, name, kw, fpb):
+    """FP32 X stage on the matrix cores: each 4x4x1 block element is a fused
+    multiply-add with one rounding, issued in the vector kernels' order, so the
+    visibilities equal the vector X stage's bit for bit (and the oracle's within
+    the FP32 tolerance)."""
+    job = configs.small_job(**kw, seed=zlib.crc32(name.encode()) % 1000)
+    V, W = fx.correlate(job, threads=8)
+    _on_gpu(xc, job)
+    try:
+        corr.set_tuning(xmac_frames_per_stage=0)
+        vec, w0 = corr.correlate(job, frames_per_block=fpb)
+        corr.set_tuning(xmac_frames_per_stage=xc.XMAC_MATRIX)
+        mat, w1 = corr.correlate(job, frames_per_block=fpb)
+        torch.cuda.synchronize()
+    finally:
+        corr.set_tuning(xmac_frames_per_stage=0)
+    assert torch.equal(w0, w1)
+    assert torch.equal(vec, mat), name
+    assert rel_l2(mat.cpu().numpy(), V) < TOL, name
+
+
 def test_tuning_variants_bit_identical(xc, corr):
     """Launch-shape variants change speed only: visibilities must be bit-identical
     (F-stage variants 1, 3, 4 and the dual-pol default 8, whose pols share their
@@ -393,6 +432,7 @@ def test_tuning_variants_bit_identical(xc, corr):
                      dict(xmac_frames_per_stage=1, xmac_channels_per_wg=32),
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=1),
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=3, xmac_channels_per_wg=16),
+                     dict(xmac_frames_per_stage=3),
                      dict(fstage_waves_per_simd=1), dict(fstage_waves_per_simd=3),
                      dict(fstage_waves_per_simd=4), dict(fstage_waves_per_simd=8)]:
             base = dict(fstage_waves_per_simd=0, xmac_frames_per_stage=0, xmac_channels_per_wg=0,
