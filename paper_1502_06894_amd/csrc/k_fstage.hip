@@ -159,7 +159,9 @@ __device__ __forceinline__ void fstage_task(
   constexpr bool kShare = F::kShare, kRamp = F::kRamp, kLean = F::kLean, kFdStep = F::kFdStep;
   const double nc0 = (double)(t - N / 2);     // centred index of the thread's first sample
   constexpr double TD = (double)T;
-  const bool in_blk = fl < nf;
+  // (one frame per task: every task's frame is in the block, and the spectra
+  // epilogue is unconditional, so nothing it loads early sinks below the FFT)
+  const bool in_blk = F::G == 1 || fl < nf;
   const bool valid = r.valid != 0;
   const float* lut_t = lut + (valid ? 0 : 4);
   // fractional-delay phasors of this thread's kept output bins
@@ -257,8 +259,15 @@ __device__ __forceinline__ void fstage_task(
     }
     if (in_blk) {
       const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
-      const int8_t* ex = OUT == kOutF32 ? nullptr
-                                        : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
+      // the exponents of this thread's eight output channels t + r n_chan / 8:
+      // one 8-byte word (loaded after the transforms: held across them, its
+      // two registers push the lean tasks' FFT addresses into scratch)
+      uint2 ex8 = make_uint2(0u, 0u);
+      if constexpr (OUT != kOutF32) {
+        static_assert(BL == 1 && T * 8 == N / 2, "thread t keeps bins t + r T, r < 8");
+        ex8 = *reinterpret_cast<const uint2*>(scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan +
+                                              (size_t)t * 8);
+      }
 #pragma unroll
       for (int b = 0; b < BL; ++b) {
         float2 fdr = fd[b][0];
@@ -280,7 +289,10 @@ __device__ __forceinline__ void fstage_task(
             }
           } else {
             const float2 y = valid ? cmul(v[b + rr * BL], fdr) : make_float2(0.f, 0.f);
-            put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+            // byte rr of the exponent word, sign-extended
+            const uint32_t ew = rr < 4 ? ex8.x : ex8.y;
+            const int ek = (int)(ew << (24 - 8 * (rr & 3))) >> 24;
+            put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : ek);
           }
         }
       }
@@ -745,15 +757,14 @@ __global__ void __launch_bounds__(256)
     const float dd = (float)r.d;
     const int sb = in / P, p = in - sb * P;
     const size_t orow = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
-    const int8_t* ex = OUT == kOutF32 ? nullptr
-                                      : scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
+    const int8_t* ex = scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
     // v[r] = X[k1 + 16 k2] with k2 = t + r T; the kept half is k2 < 1024 (r < 8)
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = k1 + 16 * (t + q * T);
       const float2 fd = phasor_turns((float)k * dd * (1.0f / (float)kBigN));
       const float2 y = valid ? cmul(v[q], fd) : make_float2(0.f, 0.f);
-      put_spec<OUT, false>(spec, orow + k, y, OUT == kOutF32 ? 0 : (int)ex[k]);
+      put_spec<OUT, false>(spec, orow + k, y, (int)ex[scale_pos(k, n_chan)]);
     }
   }
 }

@@ -37,7 +37,7 @@ constexpr double kLevelPower = 4.304810;
 // saturation); with 16 the estimate stays within a factor 4 in power.
 constexpr int kMinScaleFrames = 16;
 
-// Per (subband, input, channel): the power-of-two exponent that brings the mean
+// Per (subband, input, channel; stored at scale_pos): the power-of-two exponent that brings the mean
 // |Y|^2 over the pre-pass frames valid for the input's station to
 // 2^(2 target_log2).  Invalid frames (zero spectra) are left out of the mean;
 // an input with fewer than kMinScaleFrames valid pre-pass frames (all of them,
@@ -69,7 +69,7 @@ __global__ void k_scales(const float2* __restrict__ spec, const DelayRec* __rest
     e = (int)lrint((double)target_log2 - l2);
     e = e < -100 ? -100 : (e > 100 ? 100 : e);
   }
-  scale_exp[i] = (int8_t)e;
+  scale_exp[i - k + scale_pos(k, n_chan)] = (int8_t)e;
 }
 
 hipError_t launch_scales(const float2* spec, const DelayRec* drec, int n_subbands, int nf, int M,
@@ -233,12 +233,13 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
       scr[i * 33 + j] = acc21[c][v];
     }
     __syncthreads();   // uniform: every wave runs CPW epilogue rounds
-    const int ej = j < M ? scale_exp[((size_t)sb * M + j) * n_chan + k] : 0;
+    const int kp = scale_pos(k, n_chan);
+    const int ej = j < M ? scale_exp[((size_t)sb * M + j) * n_chan + kp] : 0;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = 8 * (v >> 2) + 4 * g + (v & 3);
       if (i <= j && j < M) {
-        const int ei = scale_exp[((size_t)sb * M + i) * n_chan + k];
+        const int ei = scale_exp[((size_t)sb * M + i) * n_chan + kp];
         const double sc = ldexp(1.0, -(ei + ej));
         const double re = ((double)acc11[c][v] + (double)acc22[c][v]) * sc;
         const double im = ((double)acc21[c][v] - (double)scr[j * 33 + i]) * sc;

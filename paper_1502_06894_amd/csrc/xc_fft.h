@@ -199,6 +199,21 @@ __device__ inline void tw_split_fill(float2* tab, const float2* __restrict__ tw,
   }
 }
 
+// lds_pad(i + r S) for r = 0, 1, ... as one padded base plus r times a
+// constant, where that is exact: S a multiple of 32 (each step crosses S / 32
+// padding slots), or all of a butterfly's R outputs (stride S, starting on a
+// multiple of S R that divides 32) inside one 32-entry run.  Written out, the
+// compiler keeps one address per butterfly instead of one per output (R
+// registers that the lean F-stage tasks would otherwise spill).
+template <int S, int R>
+constexpr bool pad_linear() {
+  return S % 32 == 0 || (S * R <= 32 && 32 % (S * R) == 0);
+}
+template <int S>
+constexpr int pad_stride() {
+  return S % 32 == 0 ? S + S / 32 : S;
+}
+
 // One Stockham pass of radix R with sub-transform length Ns over a frame of N
 // points.  On entry v[b + r B] (B = E/R) is input r of butterfly j = t + b T;
 // the outputs are written to lds; the caller synchronises.
@@ -219,8 +234,14 @@ __device__ inline void stockham_pass(float2 (&v)[E], float2* lds, const TW& tw, 
     }
     Dft<R>::run(u);
     const int idx = (j / Ns) * Ns * R + (j % Ns);
+    if constexpr (pad_linear<Ns, R>()) {
+      float2* o = lds + lds_pad(idx);
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[lds_pad(idx + r * Ns)] = u[r];
+      for (int r = 0; r < R; ++r) o[r * pad_stride<Ns>()] = u[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[lds_pad(idx + r * Ns)] = u[r];
+    }
   }
 }
 
@@ -231,8 +252,14 @@ __device__ inline void stockham_gather(float2 (&v)[E], const float2* lds, int t)
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = t + b * T;
+    if constexpr ((N / R) % 32 == 0) {
+      const float2* x = lds + lds_pad(j);
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b + r * B] = lds[lds_pad(j + r * (N / R))];
+      for (int r = 0; r < R; ++r) v[b + r * B] = x[r * pad_stride<N / R>()];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * B] = lds[lds_pad(j + r * (N / R))];
+    }
   }
 }
 

@@ -71,6 +71,14 @@ constexpr int kOutF32 = 0;   // float2
 constexpr int kOutF16 = 1;   // (Re, Im) FP16, scaled by 2^scale_exp
 constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, saturated at 448
 inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
+// The exponents of the low-precision outputs, int8 [n_subbands][M][n_chan / 8][8]:
+// channel k of a row sits at byte scale_pos(k), so that F-stage thread t,
+// whose kept bins are k = t + r n_chan / 8 (r < 8), finds its eight exponents
+// in one aligned 8-byte word.
+__host__ __device__ inline int scale_pos(int k, int n_chan) {
+  const int q = n_chan >> 3;
+  return (k & (q - 1)) * 8 + k / q;
+}
 
 // waves: F-stage variant (0 = default: kFstageLean for N >= kLeanMinN, else one task per
 // station and frame group; 1 = the latter at every N; 2..5, 7, 8 as the tuning field
@@ -109,7 +117,7 @@ hipError_t launch_fstage(int N, const DevJob* job, int n_stations, int n_inputs,
 // Scratch the F stage needs for nf frames (nonzero for N = 32768: its four-step
 // FFT goes through memory).
 size_t fstage_scratch_bytes(int N, int n_stations, int n_inputs, int nf, int out);
-// Power-of-two exponents per (subband, input, channel) that bring the mean
+// Power-of-two exponents per (subband, input, channel) (at scale_pos) that bring the mean
 // |Y|^2 of the first nf frames (FP32 spectra [n_sb][nf][M][n_chan]) to
 // target_log2 (i.e. RMS 2^target_log2), averaged over the frames that drec
 // ([n_stations][nf], input m = s P + p) marks valid; an input with no valid
