@@ -258,7 +258,10 @@ __device__ __forceinline__ void fstage_task(
       fft_forward<N>(v, lds, TwSplit<N>{tw_tab}, t);
     }
     if (in_blk) {
-      const size_t row = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
+      // FP32 row of this input; low precision: the input's place in the
+      // frame's channel-blocked run (channel k adds (k / 16) 16 M + k mod 16)
+      const size_t row = OUT == kOutF32 ? ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan
+                                        : (size_t)(sb * nf + fl) * M * n_chan + (s * P + p) * 16;
       // the exponents of this thread's eight output channels t + r n_chan / 8:
       // one 8-byte word (loaded after the transforms: held across them, its
       // two registers push the lean tasks' FFT addresses into scratch)
@@ -292,7 +295,8 @@ __device__ __forceinline__ void fstage_task(
             // byte rr of the exponent word, sign-extended
             const uint32_t ew = rr < 4 ? ex8.x : ex8.y;
             const int ek = (int)(ew << (24 - 8 * (rr & 3))) >> 24;
-            put_spec<OUT>(spec, row + k, y, OUT == kOutF32 ? 0 : ek);
+            put_spec<OUT>(spec, row + (OUT == kOutF32 ? k : (k >> 4) * 16 * M + (k & 15)), y,
+                          OUT == kOutF32 ? 0 : ek);
           }
         }
       }
@@ -756,7 +760,6 @@ __global__ void __launch_bounds__(256)
     const bool valid = r.valid != 0;
     const float dd = (float)r.d;
     const int sb = in / P, p = in - sb * P;
-    const size_t orow = ((size_t)(sb * nf + fl) * M + (s * P + p)) * n_chan;
     const int8_t* ex = scale_exp + ((size_t)sb * M + (s * P + p)) * n_chan;
     // v[r] = X[k1 + 16 k2] with k2 = t + r T; the kept half is k2 < 1024 (r < 8)
 #pragma unroll
@@ -764,7 +767,8 @@ __global__ void __launch_bounds__(256)
       const int k = k1 + 16 * (t + q * T);
       const float2 fd = phasor_turns((float)k * dd * (1.0f / (float)kBigN));
       const float2 y = valid ? cmul(v[q], fd) : make_float2(0.f, 0.f);
-      put_spec<OUT, false>(spec, orow + k, y, (int)ex[scale_pos(k, n_chan)]);
+      put_spec<OUT, false>(spec, lp_index((size_t)sb * nf + fl, s * P + p, k, M, n_chan), y,
+                           (int)ex[scale_pos(k, n_chan)]);
     }
   }
 }

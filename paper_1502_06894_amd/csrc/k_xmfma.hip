@@ -4,10 +4,12 @@
 // (2M x frames, each input scaled by a power of two before rounding).  The
 // Hermitian product splits into real products over frames:
 //   V_re = Re Re^T + Im Im^T,   V_im = Im Re^T - (Im Re^T)^T,
-// so three 32x32 MFMA tiles per channel (G11 = Re Re^T, G22 = Im Im^T,
-// G21 = Im Re^T) accumulate in FP32 with K = frames.  A workgroup owns KC
-// channels of one subband; spectra arrive in the F stage's [frame][input]
-// [channel] order.  FP16 keeps that order in LDS, rows padded to RW + 1 words
+// so per channel two 32x32 MFMA accumulators in FP32 with K = frames: one
+// takes both Re Re^T and Im Im^T (V_re directly), the other G21 = Im Re^T.
+// A workgroup owns one 16-channel tile of one subband; the F stage writes the
+// low-precision spectra channel-blocked ([frame][tile][input][16 channels]),
+// so a frame of the tile is one contiguous run of M rows.  FP16 keeps the
+// [frame][input][channel] order in LDS, rows padded to RW + 1 words
 // and frames to 32 (RW + 1) + 1, so that both the row-wise stores
 // (consecutive lanes, consecutive words) and each lane's operand gather (one
 // word per frame, 32 lanes 32 inputs apart) hit distinct banks.  FP8 (half the
@@ -106,8 +108,8 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
   // workgroup b takes tile (b mod 8) (tiles / 8) + b / 8; each XCD then works
-  // through a contiguous run of channel tiles, and tiles that share cache lines
-  // (FP16 rows of 64 B, FP8 rows of 32 B in 128-byte lines) share one L2.
+  // through a contiguous run of channel tiles, which in every frame are one
+  // contiguous stretch of memory.
   const int n_tiles = gridDim.x * gridDim.y;
   const int b = blockIdx.x + gridDim.x * blockIdx.y;
   const int tile = n_tiles % 8 == 0 ? (b % 8) * (n_tiles / 8) + b / 8 : b;
@@ -115,23 +117,23 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
   const int k0 = (tile - sb * gridDim.x) * KC;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 31, g = lane >> 5;
-  const size_t row_words = OUT == kOutF16 ? (size_t)n_chan : (size_t)n_chan / 2;   // per spectrum row
-  const uint32_t* src = spec + (size_t)sb * nf * M * row_words + (size_t)k0 * RW / KC;
+  static_assert(KC == 16, "one channel tile of the blocked spectra per workgroup");
+  // this tile's run in frame f: src + f * fstride, M rows of RW words
+  const size_t fstride = (size_t)(n_chan / 16) * M * RW;
+  const uint32_t* src = spec + ((size_t)sb * nf * (n_chan / 16) + k0 / 16) * M * RW;
 
   // inputs m >= M (and the padding) read zeros
   for (int q = threadIdx.x; q < 2 * STAGE; q += NT) lds[q] = 0u;
 
-  float16_t acc11[CPW], acc22[CPW], acc21[CPW];
+  float16_t accre[CPW], acc21[CPW];
 #pragma unroll
   for (int c = 0; c < CPW; ++c) {
-    acc11[c] = (float16_t){};
-    acc22[c] = (float16_t){};
+    accre[c] = (float16_t){};
     acc21[c] = (float16_t){};
   }
 
-  // stage loader: FB frames x M inputs x RW words, read along the channel words
-  // in 16-byte pieces (coalesced; a row starts 16-byte aligned) and stored word
-  // by word
+  // stage loader: FB frames x M inputs x RW words, each frame's M rows one
+  // contiguous run, read in 16-byte pieces and stored word by word
   constexpr int VEC = 4;
   static_assert(RW % VEC == 0, "rows of whole 16-byte pieces");
   constexpr int RV = RW / VEC;                       // pieces per row
@@ -145,7 +147,7 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
       const int w = (q % RV) * VEC, r = q / RV;      // r = fb * M + input
       const int fb = r / M, mm = r - fb * M;
       pre[i] = (r < FB * M && fb < nfb)
-                   ? *reinterpret_cast<const uint4*>(src + ((size_t)(f0 + fb) * M + mm) * row_words + w)
+                   ? *reinterpret_cast<const uint4*>(src + (size_t)(f0 + fb) * fstride + mm * RW + w)
                    : make_uint4(0u, 0u, 0u, 0u);
     }
   };
@@ -193,8 +195,8 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
             re[e] = __builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
             im[e] = __builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
           }
-          acc11[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(re, re, acc11[c], 0, 0, 0);
-          acc22[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, im, acc22[c], 0, 0, 0);
+          accre[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(re, re, accre[c], 0, 0, 0);
+          accre[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, im, accre[c], 0, 0, 0);
           acc21[c] = __builtin_amdgcn_mfma_f32_32x32x8f16(im, re, acc21[c], 0, 0, 0);
         } else {
           // 8 frames of input m, channel ch: half-word (ch & 1) of word ch / 2
@@ -210,8 +212,8 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
             re |= (uint64_t)(h & 0xffu) << (8 * e);
             im |= (uint64_t)(h >> 8) << (8 * e);
           }
-          acc11[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)re, (long)re, acc11[c], 0, 0, 0);
-          acc22[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)im, (long)im, acc22[c], 0, 0, 0);
+          accre[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)re, (long)re, accre[c], 0, 0, 0);
+          accre[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)im, (long)im, accre[c], 0, 0, 0);
           acc21[c] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8((long)im, (long)re, acc21[c], 0, 0, 0);
         }
       }
@@ -241,7 +243,7 @@ __global__ void __launch_bounds__(64 * (KC / CPW))
       if (i <= j && j < M) {
         const int ei = scale_exp[((size_t)sb * M + i) * n_chan + kp];
         const double sc = ldexp(1.0, -(ei + ej));
-        const double re = ((double)acc11[c][v] + (double)acc22[c][v]) * sc;
+        const double re = (double)accre[c][v] * sc;
         const double im = ((double)acc21[c][v] - (double)scr[j * 33 + i]) * sc;
         double2* o = vacc + ((size_t)sb * nbl + bl_of(i, j, M)) * n_chan + k;
         double2 a = *o;

@@ -65,12 +65,21 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s);
 // zeroes the F stage's task counter *ctr when ctr is not null.
 hipError_t launch_delays(const DevJob* job, int n_stations, int n_subbands, int64_t f0, int nf,
                          DelayRec* drec, PhaseRec* prec, unsigned* ctr, hipStream_t s);
-// A2-A5: spectra [n_subbands][nf][M][n_chan] for the block's frames.
+// A2-A5: spectra [n_subbands][nf][M][n_chan] for the block's frames (FP32;
+// the low-precision ones channel-blocked, see lp_index).
 // Spectrum element types written by the F stage.
 constexpr int kOutF32 = 0;   // float2
 constexpr int kOutF16 = 1;   // (Re, Im) FP16, scaled by 2^scale_exp
 constexpr int kOutF8 = 2;    // (Re, Im) OCP e4m3, scaled by 2^scale_exp, saturated at 448
 inline int out_elem_bytes(int out) { return out == kOutF32 ? 8 : out == kOutF16 ? 4 : 2; }
+// Low-precision spectra are channel-blocked, [n_subbands][nf][n_chan / 16][M][16]:
+// a frame's 16-channel tile of all M inputs is one contiguous run (M x 64 B in
+// FP16, M x 32 B in e4m3), the unit one MFMA X-stage workgroup reads.
+// Element (subband-frame sf = sb nf + f, input m, channel k):
+__host__ __device__ inline size_t lp_index(size_t sf, int m, int k, int M, int n_chan) {
+  return (sf * (size_t)(n_chan >> 4) + (size_t)(k >> 4)) * (size_t)(M * 16) + (size_t)m * 16 +
+         (size_t)(k & 15);
+}
 // The exponents of the low-precision outputs, int8 [n_subbands][M][n_chan / 8][8]:
 // channel k of a row sits at byte scale_pos(k), so that F-stage thread t,
 // whose kept bins are k = t + r n_chan / 8 (r < 8), finds its eight exponents
