@@ -199,19 +199,17 @@ __device__ inline void tw_split_fill(float2* tab, const float2* __restrict__ tw,
   }
 }
 
-// lds_pad(i + r S) for r = 0, 1, ... as one padded base plus r times a
-// constant, where that is exact: S a multiple of 32 (each step crosses S / 32
-// padding slots), or all of a butterfly's R outputs (stride S, starting on a
-// multiple of S R that divides 32) inside one 32-entry run.  Written out, the
-// compiler keeps one address per butterfly instead of one per output (R
-// registers that the lean F-stage tasks would otherwise spill).
-template <int S, int R>
-constexpr bool pad_linear() {
-  return S % 32 == 0 || (S * R <= 32 && 32 % (S * R) == 0);
-}
+// For every pass and gather of the plans below, lds_pad(i + r S) =
+// lds_pad(i) + r S + (r S) / 32: the stride S is a power of two and i's place
+// in its 32-entry run plus (r S) mod 32 stays below 32 (S a multiple of 32; or
+// i mod 32 < S with S R a multiple of 32; or a first pass whose R outputs start
+// on a multiple of R), so adding r S carries no padding slot beyond (r S) / 32.
+// Written as one padded base plus compile-time offsets, the compiler keeps one
+// address per butterfly instead of one per output (R registers that the lean
+// F-stage tasks would otherwise spill).
 template <int S>
-constexpr int pad_stride() {
-  return S % 32 == 0 ? S + S / 32 : S;
+constexpr int pad_off(int r) {
+  return r * S + (r * S) / 32;
 }
 
 // One Stockham pass of radix R with sub-transform length Ns over a frame of N
@@ -234,14 +232,9 @@ __device__ inline void stockham_pass(float2 (&v)[E], float2* lds, const TW& tw, 
     }
     Dft<R>::run(u);
     const int idx = (j / Ns) * Ns * R + (j % Ns);
-    if constexpr (pad_linear<Ns, R>()) {
-      float2* o = lds + lds_pad(idx);
+    float2* o = lds + lds_pad(idx);
 #pragma unroll
-      for (int r = 0; r < R; ++r) o[r * pad_stride<Ns>()] = u[r];
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[lds_pad(idx + r * Ns)] = u[r];
-    }
+    for (int r = 0; r < R; ++r) o[pad_off<Ns>(r)] = u[r];
   }
 }
 
@@ -252,14 +245,9 @@ __device__ inline void stockham_gather(float2 (&v)[E], const float2* lds, int t)
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int j = t + b * T;
-    if constexpr ((N / R) % 32 == 0) {
-      const float2* x = lds + lds_pad(j);
+    const float2* x = lds + lds_pad(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b + r * B] = x[r * pad_stride<N / R>()];
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[b + r * B] = lds[lds_pad(j + r * (N / R))];
-    }
+    for (int r = 0; r < R; ++r) v[b + r * B] = x[pad_off<N / R>(r)];
   }
 }
 
