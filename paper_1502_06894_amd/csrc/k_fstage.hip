@@ -876,6 +876,12 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
         // centred index of sample n is n - 16384: t - 16384 + e T (lo), t + e T (hi);
         // exact phasors every 8 samples where the quadratic term matters, else once
         const bool quad = fabs(phi2) * TD * TD * (double)(E * (E - 1)) > 1e-8;
+        // the thread index through an empty asm: the anchors' FP64 sample
+        // positions below are recomputed here rather than hoisted out of the
+        // loops and kept in scratch (the 1024-thread workgroup leaves 128
+        // registers)
+        int tq = t;
+        __asm__ volatile("" : "+v"(tq));
         float2 v[E];
         auto anchor = [&](double nc, float2& z, float2& w) {
           z = phasor_turns(frac_f(fma(fma(phi2, nc, phi1), nc, phi0)));
@@ -891,8 +897,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             if (e % 8 == 0) {
-              anchor((double)(t - kHalfN) + (double)e * TD, zl, wl);
-              anchor((double)t + (double)e * TD, zh, wh);
+              anchor((double)(tq - kHalfN) + (double)e * TD, zl, wl);
+              anchor((double)tq + (double)e * TD, zh, wh);
             } else {
               zl = cmul(zl, wl);
               zh = cmul(zh, wh);
@@ -902,8 +908,8 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(1, FftPlan<kHalfN>::T
             sample(e, zl, zh);
           }
         } else {
-          anchor((double)(t - kHalfN), zl, wl);
-          anchor((double)t, zh, wh);
+          anchor((double)(tq - kHalfN), zl, wl);
+          anchor((double)tq, zh, wh);
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             if (e > 0) {
