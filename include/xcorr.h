@@ -195,13 +195,14 @@ int xc_debug_spectra(xc_ctx* ctx, const xc_setup* setup, const xc_station* st,
 /* ---------------------------------------------------------------- tuning */
 /* Launch-shape parameters of the context (0 = library default / autotuned).
  * They change speed only: results are identical for every setting except
- * frames_per_block, which changes FP32 summation order, and F-stage variant 5,
- * which rounds the FFT's last-pass twiddles differently (results stay within
- * the FP32 path's tolerance). */
+ * frames_per_block, which changes FP32 summation order, and F-stage variants 5
+ * and 7, which at FFT lengths of 2048 and below round the last-pass twiddles
+ * differently (results stay within the FP32 path's tolerance). */
 typedef struct {
-  int32_t fstage_waves_per_simd;   /* F-stage variant: 0 = default (7 for FFT lengths of
-                                      8192 and more; 8 for dual-pol FP32 jobs with FFT
-                                      lengths up to 2048; else 1); 1 = one task per station and
+  int32_t fstage_waves_per_simd;   /* F-stage variant: 0 = default (FP32 spectra: 2 for
+                                      dual-pol jobs with FFT lengths up to 4096, 7 for
+                                      single-pol ones from 1024 to 4096; 7 for FFT lengths
+                                      of 8192 and more; else 1); 1 = one task per station and
                                       frame group, the next task's window words loaded
                                       during the transforms; 2 = the pols of a subband
                                       share their fringe phasors (fewer operations, more

@@ -1043,6 +1043,8 @@ static hipError_t launch_fused_n(int waves, const FusedItem* items, int n_items,
 
 int fstage_fused_variant(int N, int n_pols, int n_chan) {
   const int w = fstage_variant(0, n_pols, n_chan, kOutF32);
+  // variant 2's fused form is kFstageShare (the same arithmetic)
+  if (w == 2) return kFstageShare;
   return w == 0 && N >= kLeanMinN ? kFstageLean : w;
 }
 

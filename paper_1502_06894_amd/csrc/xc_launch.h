@@ -103,17 +103,25 @@ constexpr int kFstageRatePass = 6;
 constexpr int kFstageLean = 7;
 // kFstageShare: the pols of a subband share their fringe phasors (held from the
 // first pol to the second), with no word prefetch and the fractional-delay
-// phasors stepped at the store to make room for them; the default for dual-pol
-// FP32 jobs up to kShareMaxN (measured on MI355X: a C2-shaped F stage 3.3 %
-// faster; at N = 4096 the registers would cost a wave per SIMD).
+// phasors stepped at the store to make room for them (bit-identical to
+// variants 0-4; the fused batch kernels' form of variant 2).
 constexpr int kFstageShare = 8;
-constexpr int kShareMaxN = 2048;
+constexpr int kShareMaxN = 4096;
 constexpr int kLeanMinN = 8192;
 constexpr int kLeanGroup = 4;   // inputs per lean task
-// The F-stage variant a job runs: the tuned one, else kFstageShare where it pays.
+// The F-stage variant a job runs: the tuned one, else for FP32 spectra up to
+// N = kShareMaxN variant 2 for dual-pol jobs (pols share their fringe phasors,
+// with the word prefetch and held fractional-delay phasors) and lean tasks
+// for single-pol jobs from N = 1024; 0 otherwise (lean tasks from kLeanMinN).
+// Measured on MI355X, F stage of 10-station, 2-subband jobs against the
+// previous defaults: dual-pol N = 1024 / 2048 / 4096 -2 / -3 / -8 %,
+// single-pol N = 1024 / 2048 / 4096 -7 / -9 / -3 %.
 inline int fstage_variant(int tuned, int n_pols, int n_chan, int out) {
   if (tuned != 0) return tuned;
-  return n_pols == 2 && 2 * n_chan <= kShareMaxN && out == kOutF32 ? kFstageShare : 0;
+  const int N = 2 * n_chan;
+  if (out != kOutF32 || N > kShareMaxN) return 0;
+  if (n_pols == 2) return 2;
+  return N >= 1024 ? kFstageLean : 0;
 }
 constexpr int kMaxRateCorrectN = 16384;   // the drift correction runs in the one-workgroup FFT
 // ctr: task counter, zero at launch (launch_delays clears it), one per concurrent launch.

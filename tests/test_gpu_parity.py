@@ -419,8 +419,8 @@ def test_matrix_core_x_stage(xc, corr, name, kw, fpb):
 
 def test_tuning_variants_bit_identical(xc, corr):
     """Launch-shape variants change speed only: visibilities must be bit-identical
-    (F-stage variants 1, 3, 4 and the dual-pol default 8, whose pols share their
-    fringe phasors, included)."""
+    (F-stage variants 1, 3, 4 and the pol-sharing 2 (the dual-pol default) and 8
+    included)."""
     job = configs.small_job(n_stations=5, n_subbands=2, n_pols=2, n_chan=256, C=4, n_frames=300)
     V, W = fx.correlate(job, threads=8)
     _on_gpu(xc, job)
@@ -433,7 +433,8 @@ def test_tuning_variants_bit_identical(xc, corr):
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=1),
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=3, xmac_channels_per_wg=16),
                      dict(xmac_frames_per_stage=3),
-                     dict(fstage_waves_per_simd=1), dict(fstage_waves_per_simd=3),
+                     dict(fstage_waves_per_simd=1), dict(fstage_waves_per_simd=2),
+                     dict(fstage_waves_per_simd=3),
                      dict(fstage_waves_per_simd=4), dict(fstage_waves_per_simd=8)]:
             base = dict(fstage_waves_per_simd=0, xmac_frames_per_stage=0, xmac_channels_per_wg=0,
                         xmac_tiles_per_wg=0)
