@@ -276,12 +276,40 @@ def _counter_means(db_path: str, counter: str) -> dict:
     return {k: tot / n for k, (n, tot) in agg.items()}
 
 
+# The C2 workload's F and X kernels in a counter database: the F-stage and
+# X-stage kernels of its FFT length and input count, whatever variant the
+# library's defaults pick (the one with the most dispatches).
+C2_KERNELS = {"fstage": ("xc::k_fstage<2048,", F_SOURCES), "xmac": ("xc::k_xmac_ring<20,", X_SOURCES)}
+
+
+def _resolve_kernels(counts: dict, kernels: dict) -> dict:
+    out = {}
+    for kind, (prefix, srcs) in kernels.items():
+        names = [n for n in counts if n.startswith(prefix)]
+        if not names:
+            raise SystemExit(f"no kernel {prefix}... in the counter database")
+        out[kind] = (max(names, key=lambda n: counts[n]), srcs)
+    return out
+
+
+def _dispatch_counts(db_path: str, counter: str) -> dict:
+    import sqlite3
+    cur = sqlite3.connect(db_path).cursor()
+    n = {}
+    for kn, cn in cur.execute("select kernel_name, counter_name from counters_collection"):
+        if cn == counter:
+            k = short_kernel_name(kn)
+            n[k] = n.get(k, 0) + 1
+    return n
+
+
 def valu_json(db: str, ss_per_launch: float, kernels: dict) -> dict:
     """VALU instructions per station-sample (SQ_INSTS_VALU x 64 / ss) and VALU
     busy (SQ_ACTIVE_INST_VALU / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs)) per kernel kind."""
     insts = _counter_means(db, "SQ_INSTS_VALU")
     active = _counter_means(db, "SQ_ACTIVE_INST_VALU")
     grbm = _counter_means(db, "GRBM_GUI_ACTIVE")
+    kernels = _resolve_kernels(_dispatch_counts(db, "SQ_INSTS_VALU"), kernels)
     out = {"ss_per_launch": ss_per_launch}
     for kind, (name, srcs) in kernels.items():
         out[kind] = {"kernel": name, "source_hash": kernel_source_hash(srcs),
@@ -301,6 +329,7 @@ def traffic_json(fetch_db: str, write_db: str, copy_fetch_db: str, copy_write_db
     sf, sw = copy_kib / cf, copy_kib / cw
     fetch = _counter_means(fetch_db, "FETCH_SIZE")
     write = _counter_means(write_db, "WRITE_SIZE")
+    kernels = _resolve_kernels(_dispatch_counts(fetch_db, "FETCH_SIZE"), kernels)
     out = {"fetch_scale": sf, "write_scale": sw, "ss_per_launch": ss_per_launch}
     for kind, (name, srcs) in kernels.items():
         fb = fetch[name] * sf * 1024.0
@@ -871,17 +900,13 @@ def main():
         print(rocpd_summary(a.rocpd_summary))
         return
     if a.valu_json:
-        d = valu_json(a.valu_json, a.ss_per_launch,
-                      {"fstage": ("xc::k_fstage<2048, 8, 0>", F_SOURCES),
-                       "xmac": ("xc::k_xmac_ring<20, false>", X_SOURCES)})
+        d = valu_json(a.valu_json, a.ss_per_launch, C2_KERNELS)
         with open(os.path.join(ROOT, "profiles", "valu_counters.json"), "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d, indent=1))
         return
     if a.traffic_json:
-        d = traffic_json(*a.traffic_json, a.ss_per_launch,
-                         {"fstage": ("xc::k_fstage<2048, 8, 0>", F_SOURCES),
-                          "xmac": ("xc::k_xmac_ring<20, false>", X_SOURCES)})
+        d = traffic_json(*a.traffic_json, a.ss_per_launch, C2_KERNELS)
         with open(os.path.join(ROOT, "profiles", "hbm_counters.json"), "w") as fh:
             json.dump(d, fh, indent=1)
         print(json.dumps(d, indent=1))
