@@ -2,7 +2,7 @@
 // Y_i[k] conj(Y_j[k]) over the block's frames for all input pairs i <= j.
 //
 // A workgroup owns KC consecutive channels of one subband and one slice of
-// the block's frames (at most 256).  Inputs are grouped four at a time;
+// the block's frames (at most 1024).  Inputs are grouped four at a time;
 // thread (channel c, tile (gi, gj)) accumulates the 4 x 4 block of products
 // between groups gi <= gj in FP32 registers over its frame slice, then adds it
 // to the FP64 accumulator slot of that slice.  Every output element of a slot
@@ -736,12 +736,22 @@ static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subb
 }
 
 int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands) {
-  // 512-frame slices halve the FP64 slot traffic; taken when the 64-channel
-  // tiles still give at least 512 workgroups (two per compute unit)
+  // Longer slices cut the FP64 slot traffic (one read and write of the slot
+  // per slice).  1024-frame slices where the ring's workgroups still give at
+  // least three waves per SIMD (C2: X stage 16.2 -> 15.6 ms per step; whole
+  // 2048-frame blocks leave half the CUs idle: 24.4 ms); else 512-frame
+  // slices where the 64-channel tiles give at least 512 workgroups (two per
+  // compute unit); else 256.
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
   const long zchunks = (ntiles + 15) / 16;
+  if (Mp <= 32 && n_chan % 64 == 0) {
+    int tpw, zc, waves;
+    ring_shape(Mp, tpw, zc, waves);
+    const long wgs1k = (long)(n_chan / 64) * n_subbands * zc * ((T + 1023) / 1024);
+    if (wgs1k * waves >= 3L * 1024) return 1024;
+  }
   const long wgs = (long)(n_chan / 64) * n_subbands * zchunks * ((T + 511) / 512);
   return wgs >= 512 ? 512 : 256;
 }

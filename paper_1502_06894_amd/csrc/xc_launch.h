@@ -147,9 +147,9 @@ hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_sub
                         const void* spec, const int8_t* scale_exp, double2* vacc,
                         size_t slot_stride, int nf, hipStream_t s);
 // Frames (at most) one X workgroup accumulates in FP32 before adding to its
-// FP64 slot, for blocks of T frames of a job with M inputs per subband: 512
-// when that still gives the GPU enough workgroups, else 256.  A block of nf
-// frames uses ceil(nf / that) slots.
+// FP64 slot, for blocks of T frames of a job with M inputs per subband: 1024
+// or 512 when that still gives the GPU enough workgroups, else 256.  A block
+// of nf frames uses ceil(nf / that) slots.
 int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands);
 // A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
 // (double2), slot_stride elements apart; fps: xmac_frames_per_split of the job.
