@@ -383,6 +383,11 @@ def _batch_fpb(job, tuned_fpb=0, elem_bytes=8):
     return _shared_fpb(job, T, 1 << 30, 64, elem_bytes)
 
 
+# X-stage staging values of the library's tuning record, by name
+XSTAGING = {0: "default", 1: "direct", 2: "2-frame stages", 3: "matrix cores",
+            4: "4-frame stages", 5: "matrix cores through the ring", 8: "ring"}
+
+
 def run_c3(a):
     """64 uneven sub-integrations over a device-resident pool: the fused batch
     executor (one persistent F-stage launch per FFT length and round) and the
@@ -410,8 +415,8 @@ def run_c3(a):
         torch.cuda.synchronize()
     picks = {}
     for t in tuned:
-        key = (f"fpb {t.get('frames_per_block', 0)}, X stage "
-               f"{ {8: 'ring', 4: '4-frame stages', 3: 'matrix cores', 2: '2-frame stages', 1: 'direct', 0: 'default'}[t.get('xmac_frames_per_stage', 0)] }"
+        xs = t.get("xmac_frames_per_stage", 0)
+        key = (f"fpb {t.get('frames_per_block', 0)}, X stage {XSTAGING.get(xs, f'staging {xs}')}"
                + (f" {t['xmac_channels_per_wg']} ch" if t.get("xmac_channels_per_wg") else ""))
         picks[key] = picks.get(key, 0) + 1
     fpbs = [_batch_fpb(j, t.get("frames_per_block", 0)) for j, t in zip(jobs, tuned)]
@@ -656,7 +661,8 @@ def run_c5(a):
 
 def run_xcross(a):
     """X stage on the vector ALUs (FP32), on the matrix cores in FP32 (the same
-    fused multiply-adds, bit-identical sums) and on MFMA in FP16 / e4m3, as the
+    fused multiply-adds, bit-identical sums; operands loaded per wave or fed
+    through the LDS ring) and on MFMA in FP16 / e4m3, as the
     number of inputs per subband grows: C4-shaped jobs (4 x 32 MHz subbands,
     4096 channels, 1024 frames) with M = 4 .. 32 stations, X-stage kernel time
     per job from HIP events."""
@@ -667,8 +673,8 @@ def run_xcross(a):
     rows = []
     # (name, precision, X staging): FP32 on the vector ALUs through the LDS
     # ring, FP32 on the matrix cores, FP16 / e4m3 on MFMA
-    variants = (("fp32", "fp32", 8), ("fp32m", "fp32", xcorr.XMAC_MATRIX), ("fp16", "fp16", 0),
-                ("fp8", "fp8", 0))
+    variants = (("fp32", "fp32", 8), ("fp32m", "fp32", xcorr.XMAC_MATRIX),
+                ("fp32mr", "fp32", xcorr.XMAC_MATRIX_RING), ("fp16", "fp16", 0), ("fp8", "fp8", 0))
     for M in (4, 8, 12, 16, 20, 24, 28, 32):
         job = configs.c4_job(device="cuda", n_stations=M, n_frames=1024)
         xcorr.job_to_device(job, "cuda:0")
@@ -698,9 +704,12 @@ def run_xcross(a):
             del ws, out
         corr.set_tuning(xmac_frames_per_stage=0)
         row["fp32m_bit_identical"] = bool(torch.equal(vis32["fp32"], vis32["fp32m"]))
+        row["fp32mr_bit_identical"] = bool(torch.equal(vis32["fp32"], vis32["fp32mr"]))
         rows.append(row)
         log(f"M = {M:2d}: X stage FP32 vector {row['fp32']['x_ms']:.3f} ms, matrix "
             f"{row['fp32m']['x_ms']:.3f} ms (identical: {row['fp32m_bit_identical']}), "
+            f"matrix through the ring {row['fp32mr']['x_ms']:.3f} ms (identical: "
+            f"{row['fp32mr_bit_identical']}), "
             f"FP16 {row['fp16']['x_ms']:.3f} ms, e4m3 {row['fp8']['x_ms']:.3f} ms")
         del job, vis32
         torch.cuda.synchronize()

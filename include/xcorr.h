@@ -221,16 +221,21 @@ typedef struct {
                                       phasors stepped at the store (bit-identical to 1).
                                       2-4 and 8 apply to FP32 spectra only. */
   int32_t xmac_frames_per_stage;   /* X-stage input staging: 8 = ring of 8 one-frame LDS
-                                      stages filled by direct memory-to-LDS loads (64-channel
-                                      tiles, at most 32 inputs per subband; the default where
-                                      it applies, except for 21-24 and 29-32 inputs per
-                                      subband, where 3 is); 2 or 4 = double-buffered stages of that many
-                                      frames through registers (the default otherwise);
+                                      stages filled by direct memory-to-LDS loads, products
+                                      on the vector units (64-channel tiles, at most 32
+                                      inputs per subband); 2 or 4 = double-buffered stages
+                                      of that many frames through registers (the default
+                                      above 32 inputs per subband);
                                       1 = no LDS staging (inputs read from memory, one frame
                                       ahead); 3 = the FP32 products on the matrix cores
                                       (v_mfma_f32_4x4x1: 16 channels per wave, inputs read
                                       from memory a few frames ahead, at most 32 inputs per
-                                      subband, channels a multiple of 16); 0 = default.
+                                      subband, channels a multiple of 16); 5 = the same
+                                      matrix-core products fed through the ring of 8 LDS
+                                      stages (each input loaded once per 64-channel
+                                      workgroup; at most 32 inputs per subband, channels a
+                                      multiple of 64; the default where it applies, and the
+                                      X stage of fused batches); 0 = default.
                                       Every staging gives bit-identical visibilities: the
                                       matrix cores' products are fused multiply-adds with
                                       one rounding, issued in the vector kernels' order */

@@ -696,10 +696,10 @@ int xc_autotune(xc_ctx* c, const xc_setup* setup, const xc_station* st, const xc
     if (fpb > s.n_frames && fpb != 512) continue;
     if (s.precision == XC_FP32) {
       const int M = s.n_stations * s.n_pols;
-      const int xs[][2] = {{0, 0}, {8, 0}, {kXmacMatrix, 0}, {2, 0}, {4, 0}, {2, 32}, {1, 0}};
+      const int xs[][2] = {{0, 0}, {8, 0}, {kXmacMatrix, 0}, {kXmacMatrixRing, 0}, {2, 0}, {4, 0}, {2, 32}, {1, 0}};
       for (auto& x : xs) {
         // the ring and the matrix-core stage hold at most 32 inputs
-        if ((x[0] == 8 || x[0] == kXmacMatrix) && M > 32) continue;
+        if ((x[0] == 8 || x[0] == kXmacMatrix || x[0] == kXmacMatrixRing) && M > 32) continue;
         if (x[0] == 0 && fpb != 0) continue;  // (the default X stage at other block sizes:
                                              //  ring, matrix or staged kernel, listed)
         cands.push_back({0, x[0], x[1], fpb, 0, 1});

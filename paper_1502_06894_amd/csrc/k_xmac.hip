@@ -306,39 +306,17 @@ __device__ __forceinline__ void ring_mac(const float2 (&a)[kGroup], const float2
     }
 }
 
-// FUSED: one launch over the blocks of many jobs (a fused batch round) whose
-// inputs pad to the same MP: workgroup b belongs to the item whose xblk0 is
-// the last at or below b, and b - xblk0 enumerates that item's (channel tile,
-// subband, tile chunk x frame slice) as blockIdx (x, y, z) does otherwise.
-template <int MP, bool FUSED>
+template <int MP>
 __global__ void __launch_bounds__(1024)
     k_xmac_ring(const DevJob* __restrict__ job, const float2* __restrict__ spec,
                 double2* __restrict__ vacc, int nf, int tiles_per_wg, int zchunks,
-                int frames_per_split, size_t slot_stride, const FusedItem* __restrict__ items,
-                int n_items) {
+                int frames_per_split, size_t slot_stride) {
   static_assert(MP % kGroup == 0 && MP <= 32, "ring stages hold at most 32 inputs");
   static_assert(kRing == 8, "one LDS variable per stage");
   constexpr int KC = 64;
   constexpr int F4 = MP * KC / 2;     // float4 per stage
   __shared__ float4 r0[F4], r1[F4], r2[F4], r3[F4], r4[F4], r5[F4], r6[F4], r7[F4];
-  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-  if constexpr (FUSED) {
-    const int it = fused_find(items, n_items, (int)blockIdx.x,
-                              [](const FusedItem& I) { return I.xblk0; });
-    const FusedItem& I = items[it];
-    job = I.job;
-    spec = I.spec;
-    vacc = I.vacc;
-    nf = I.nf;
-    frames_per_split = I.fps;
-    slot_stride = I.slot_stride;
-    const int n_ct = job->n_chan / KC;
-    int local = (int)blockIdx.x - I.xblk0;
-    bx = local % n_ct;
-    local /= n_ct;
-    by = local % job->n_subbands;
-    bz = local / job->n_subbands;
-  }
+  const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
   const DevJob& J = *job;
   const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
   constexpr int ng = MP / kGroup;
@@ -456,8 +434,8 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
   dim3 block(64 * waves);
 #define XMAC_RING(MPV)                                                                    \
   case MPV:                                                                               \
-    hipLaunchKernelGGL((k_xmac_ring<MPV, false>), grid, block, 0, s, job, spec, vacc, nf, \
-                       tiles_per_wg, zchunks, fps, slot_stride, nullptr, 0);              \
+    hipLaunchKernelGGL((k_xmac_ring<MPV>), grid, block, 0, s, job, spec, vacc, nf,        \
+                       tiles_per_wg, zchunks, fps, slot_stride);                          \
     break;
   switch (Mp) {
     XMAC_RING(4) XMAC_RING(8) XMAC_RING(12) XMAC_RING(16) XMAC_RING(20) XMAC_RING(24)
@@ -468,16 +446,6 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
   return hipGetLastError();
 }
 
-// Ring-kernel launch shape of inputs padded to Mp: tiles per workgroup, tile
-// chunks and waves (the same for every job of that Mp).
-static void ring_shape(int Mp, int& tiles_per_wg, int& zchunks, int& waves) {
-  const int ng = Mp / kGroup;
-  const int ntiles = ng * (ng + 1) / 2;
-  tiles_per_wg = ntiles < 16 ? ntiles : 16;
-  zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
-  waves = tiles_per_wg > Mp / 2 ? tiles_per_wg : Mp / 2;
-}
-
 bool xmac_fused_ok(int M, int n_chan) {
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   return Mp <= 32 && n_chan % 64 == 0;
@@ -486,33 +454,6 @@ bool xmac_fused_ok(int M, int n_chan) {
 void xmac_splits(int nf, int fps_max, int& n_splits, int& fps) {
   n_splits = (nf + fps_max - 1) / fps_max;
   fps = (nf + n_splits - 1) / n_splits;
-}
-
-int xmac_fused_blocks(int M, int n_chan, int n_subbands, int n_splits) {
-  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
-  int tpw, zchunks, waves;
-  ring_shape(Mp, tpw, zchunks, waves);
-  return n_chan / 64 * n_subbands * zchunks * n_splits;
-}
-
-hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_blocks,
-                             hipStream_t s) {
-  if (n_blocks <= 0) return hipSuccess;
-  int tpw, zchunks, waves;
-  ring_shape(Mp, tpw, zchunks, waves);
-  const dim3 grid(n_blocks), block(64 * waves);
-#define XMAC_FUSED(MPV)                                                                   \
-  case MPV:                                                                               \
-    hipLaunchKernelGGL((k_xmac_ring<MPV, true>), grid, block, 0, s, nullptr, nullptr,     \
-                       nullptr, 0, tpw, zchunks, 0, 0, items, n_items);                   \
-    break;
-  switch (Mp) {
-    XMAC_FUSED(4) XMAC_FUSED(8) XMAC_FUSED(12) XMAC_FUSED(16) XMAC_FUSED(20) XMAC_FUSED(24)
-    XMAC_FUSED(28) XMAC_FUSED(32)
-    default: return hipErrorInvalidValue;
-  }
-#undef XMAC_FUSED
-  return hipGetLastError();
 }
 
 // Matrix-core variant: the same products on v_mfma_f32_4x4x1 (16 blocks of
@@ -702,6 +643,266 @@ static hipError_t launch_mfma(const DevJob* job, int M, int n_chan, int n_subban
   return hipGetLastError();
 }
 
+// Matrix cores fed through the LDS ring: the ring kernel's loads (one 1 KB
+// global_load_lds per wave and frame, kRing - 1 frames ahead, one barrier per
+// frame), the matrix kernel's products.  Every input is loaded once per
+// workgroup however many waves multiply it.  A workgroup owns 64 channels of
+// one subband and one frame slice; wave w multiplies channel block w % 4 (16
+// channels) over part w / 4 of the 4 x 4 tiles, and loads the row pair w.
+// Rows are paired (8q + x, 8q + 4 + x) and pair (q, x) sits at byte
+// q * kRingmQuad + x * kRingmPair of a stage, so row 4g + r of every group
+// g starts 64 r bytes into a 256-byte bank window: the 32 lanes of a half-wave
+// (8 channels x 4 rows) read 32 different 8-byte bank pairs of the 64 banks.
+// A last, half-filled quad (MP % 8 == 4) loads its rows again into the unused
+// halves.  Products are issued in the vector kernels' order, so the sums are
+// bit-identical to theirs.
+constexpr int kRingmPair = 1024 + 64;   // bytes: 64 r mod 256 for the pair at x = r
+// bytes per quad: a multiple of 512 (one LDS base register serves every row of
+// a stage: read2st64 offsets count 512-byte units)
+constexpr int kRingmQuad = 9 * 512;
+static_assert(4 * kRingmPair <= kRingmQuad && kRingmQuad % 512 == 0, "quad layout");
+
+constexpr int ringm_parts(int MP) { return (MP + 7) / 8; }
+
+// One ring step for frame j, as the ring kernel's: wait, barrier, refill RF
+// with frame j + kRing - 1, read frame j + 1 from RD into NEXT, multiply CUR.
+#define XC_RINGM_STEP(RD, RF, CUR, NEXT)                                               \
+  {                                                                                  \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(kRing - 3));                           \
+    __asm__ volatile("" ::: "memory");                                               \
+    __builtin_amdgcn_s_barrier();                                                    \
+    __asm__ volatile("" ::: "memory");                                               \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+    ring_load(gsrc + (size_t)min(j + kRing - 1, fz - 1) * fstride4 + loff, RF + wbase);\
+    read(reinterpret_cast<const float2*>(RD), NEXT);                                 \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+    mac(CUR);                                                                        \
+    ++j;                                                                             \
+  }
+
+template <int MP, int S, int PART>
+__device__ __forceinline__ void ringm_part(float4* r0, float4* r1, float4* r2, float4* r3,
+                                          float4* r4, float4* r5, float4* r6, float4* r7,
+                                          const float4* __restrict__ gsrc, int loff,
+                                          size_t fstride4, int wbase, int rbase, int fa,
+                                          int fz, int M, int n_chan, int nbl, int sb, int c,
+                                          int r, double2* __restrict__ slot) {
+  constexpr int MG = MP / kGroup;
+  constexpr MfmaTiles<MG> tiles{};
+  constexpr int NT = MfmaTiles<MG>::NT;
+  constexpr int NTW = (NT + S - 1) / S;
+  constexpr int T0 = PART * NTW;
+  constexpr int NTP = NT - T0 < NTW ? NT - T0 : NTW;
+  static_assert(NTP >= 1, "every part has a tile");
+  xm_f4 accr[NTP], acci[NTP];
+#pragma unroll
+  for (int t = 0; t < NTP; ++t) {
+    accr[t] = (xm_f4){0.f, 0.f, 0.f, 0.f};
+    acci[t] = (xm_f4){0.f, 0.f, 0.f, 0.f};
+  }
+  // row 4g + r of a stage: pair (g / 2, r), half g % 2 (groups this part's
+  // tiles never touch are not read)
+  auto read = [&](const float2* st, float2 (&x)[MG]) {
+#pragma unroll
+    for (int g = 0; g < MG; ++g) x[g] = st[rbase + (g >> 1) * (kRingmQuad / 8) + (g & 1) * 64];
+  };
+  auto mac = [&](const float2 (&x)[MG]) {
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) {
+      const float2 a = x[tiles.gi[T0 + t]], b = x[tiles.gj[T0 + t]];
+      // re: a.y b.y, then a.x b.x; im: -a.x b.y, then a.y b.x
+      accr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.y, accr[t], 0, 0, 0);
+      accr[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.x, b.x, accr[t], 0, 0, 0);
+      acci[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(-a.x, b.y, acci[t], 0, 0, 0);
+      acci[t] = __builtin_amdgcn_mfma_f32_4x4x1f32(a.y, b.x, acci[t], 0, 0, 0);
+    }
+  };
+  int j = fa;
+  ring_load(gsrc + (size_t)fa * fstride4 + loff, r0 + wbase);
+  ring_load(gsrc + (size_t)min(fa + 1, fz - 1) * fstride4 + loff, r1 + wbase);
+  ring_load(gsrc + (size_t)min(fa + 2, fz - 1) * fstride4 + loff, r2 + wbase);
+  ring_load(gsrc + (size_t)min(fa + 3, fz - 1) * fstride4 + loff, r3 + wbase);
+  ring_load(gsrc + (size_t)min(fa + 4, fz - 1) * fstride4 + loff, r4 + wbase);
+  ring_load(gsrc + (size_t)min(fa + 5, fz - 1) * fstride4 + loff, r5 + wbase);
+  ring_load(gsrc + (size_t)min(fa + 6, fz - 1) * fstride4 + loff, r6 + wbase);
+  float2 xA[MG], xB[MG];
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm_lds(kRing - 2));
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+  read(reinterpret_cast<const float2*>(r0), xA);
+  for (int round = (fz - fa) / kRing; round > 0; --round) {
+    XC_RINGM_STEP(r1, r7, xA, xB) XC_RINGM_STEP(r2, r0, xB, xA)
+    XC_RINGM_STEP(r3, r1, xA, xB) XC_RINGM_STEP(r4, r2, xB, xA)
+    XC_RINGM_STEP(r5, r3, xA, xB) XC_RINGM_STEP(r6, r4, xB, xA)
+    XC_RINGM_STEP(r7, r5, xA, xB) XC_RINGM_STEP(r0, r6, xB, xA)
+  }
+  do {
+    if (j >= fz) break;
+    XC_RINGM_STEP(r1, r7, xA, xB)
+    if (j >= fz) break;
+    XC_RINGM_STEP(r2, r0, xB, xA)
+    if (j >= fz) break;
+    XC_RINGM_STEP(r3, r1, xA, xB)
+    if (j >= fz) break;
+    XC_RINGM_STEP(r4, r2, xB, xA)
+    if (j >= fz) break;
+    XC_RINGM_STEP(r5, r3, xA, xB)
+    if (j >= fz) break;
+    XC_RINGM_STEP(r6, r4, xB, xA)
+    if (j >= fz) break;
+    XC_RINGM_STEP(r7, r5, xA, xB)
+  } while (false);
+  // no load may still be writing LDS when the workgroup ends
+  __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+  // the slot addresses are formed here, not before the loop (where the
+  // compiler would otherwise hold them through it)
+  __asm__ volatile("" : "+v"(c), "+v"(r));
+#pragma unroll
+  for (int t = 0; t < NTP; ++t) {
+    const int gi = tiles.gi[T0 + t], gj = tiles.gj[T0 + t];
+#pragma unroll
+    for (int x = 0; x < kGroup; ++x) {
+      const int i = gi * kGroup + x, jj = gj * kGroup + r;
+      if (i <= jj && jj < M) {
+        double2* o = slot + ((size_t)sb * nbl + bl_index(i, jj, M)) * n_chan + c;
+        double2 v = *o;
+        v.x += (double)accr[t][x];
+        v.y += (double)acci[t][x];
+        *o = v;
+      }
+    }
+  }
+}
+#undef XC_RINGM_STEP
+
+// FUSED: one launch over the blocks of many jobs (a fused batch round) whose
+// inputs pad to the same MP: workgroup b belongs to the item whose xblk0 is
+// the last at or below b, and b - xblk0 enumerates that item's (channel tile,
+// subband, frame slice) as blockIdx (x, y, z) does otherwise.
+template <int MP, bool FUSED>
+__global__ void __launch_bounds__(1024)
+    k_xmac_ringm(const DevJob* __restrict__ job, const float2* __restrict__ spec,
+                 double2* __restrict__ vacc, int nf, int frames_per_split, size_t slot_stride,
+                 const FusedItem* __restrict__ items, int n_items) {
+  static_assert(MP % kGroup == 0 && MP <= 32, "ring stages hold at most 32 inputs");
+  static_assert(kRing == 8, "one LDS variable per stage");
+  constexpr int S = ringm_parts(MP);
+  constexpr int F4 = S * kRingmQuad / 16;   // float4 per stage
+  __shared__ float4 r0[F4], r1[F4], r2[F4], r3[F4], r4[F4], r5[F4], r6[F4], r7[F4];
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if constexpr (FUSED) {
+    // the item table and its job descriptors as constant data (scalar loads)
+    const FusedItemsK ik = fused_const(items);
+    const int it = fused_find(ik, n_items, (int)blockIdx.x,
+                              [](const auto& I) { return I.xblk0; });
+    job = (const DevJob*)&ik[it].jd;
+    spec = ik[it].spec;
+    vacc = ik[it].vacc;
+    nf = ik[it].nf;
+    frames_per_split = ik[it].fps;
+    slot_stride = ik[it].slot_stride;
+    const int n_ct = job->n_chan / 64;
+    int local = (int)blockIdx.x - ik[it].xblk0;
+    bx = local % n_ct;
+    local /= n_ct;
+    by = local % job->n_subbands;
+    bz = local / job->n_subbands;
+  }
+  const DevJob& J = *job;
+  const int M = J.M, n_chan = J.n_chan, nbl = J.nbl;
+  const int sb = by, k0 = bx * 64;
+  const int split = bz;
+  const int fa = split * frames_per_split;
+  const int fz = min(nf, fa + frames_per_split);
+  if (fa >= fz) return;   // whole workgroup
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  // loads: row pair (q, x) = rows 8q + x and 8q + 4 + x (a row past MP: the
+  // first again; rows past M repeat row M - 1, their products never stored),
+  // float4 column lane % 32 of the 64-channel tile
+  const int q = wave >> 2, x = wave & 3;
+  const int lo = 8 * q + x, hi = lo + 4 < MP ? lo + 4 : lo;
+  const int row = min((lane >> 5) ? hi : lo, M - 1);
+  const float4* gsrc = reinterpret_cast<const float4*>(spec + (size_t)sb * nf * M * n_chan + k0);
+  const int loff = row * (n_chan / 2) + (lane & 31);
+  const size_t fstride4 = (size_t)M * n_chan / 2;
+  const int wbase = (q * kRingmQuad + x * kRingmPair) / 16;
+  // products: channel block wave % 4, part wave / 4; lane 4b + r holds row
+  // 4g + r of each group g at channel 16 (wave % 4) + b
+  const int cb = wave & 3, part = wave >> 2;
+  const int r = lane & 3, b = lane >> 2;
+  const int rbase = r * (kRingmPair / 8) + cb * 16 + b;
+  const int c = k0 + cb * 16 + b;
+  double2* slot = vacc + (size_t)split * slot_stride;
+  static_assert(S >= 1 && S <= 4, "one to four parts");
+  if (part == 0)
+    ringm_part<MP, S, 0>(r0, r1, r2, r3, r4, r5, r6, r7, gsrc, loff, fstride4, wbase, rbase, fa,
+                         fz, M, n_chan, nbl, sb, c, r, slot);
+  if constexpr (S >= 2)
+    if (part == 1)
+      ringm_part<MP, S, 1>(r0, r1, r2, r3, r4, r5, r6, r7, gsrc, loff, fstride4, wbase, rbase,
+                           fa, fz, M, n_chan, nbl, sb, c, r, slot);
+  if constexpr (S >= 3)
+    if (part == 2)
+      ringm_part<MP, S, 2>(r0, r1, r2, r3, r4, r5, r6, r7, gsrc, loff, fstride4, wbase, rbase,
+                           fa, fz, M, n_chan, nbl, sb, c, r, slot);
+  if constexpr (S >= 4)
+    if (part == 3)
+      ringm_part<MP, S, 3>(r0, r1, r2, r3, r4, r5, r6, r7, gsrc, loff, fstride4, wbase, rbase,
+                           fa, fz, M, n_chan, nbl, sb, c, r, slot);
+}
+
+static hipError_t launch_ringm(const DevJob* job, int M, int n_chan, int n_subbands,
+                               const float2* spec, double2* vacc, size_t slot_stride, int nf,
+                               int fps_max, hipStream_t s) {
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  if (Mp > 32 || n_chan % 64 != 0) return hipErrorInvalidValue;
+  int n_splits, fps;
+  xmac_splits(nf, fps_max, n_splits, fps);
+  dim3 grid(n_chan / 64, n_subbands, n_splits);
+  dim3 block(256 * ringm_parts(Mp));
+#define XMAC_RINGM(MPV)                                                                   \
+  case MPV:                                                                               \
+    hipLaunchKernelGGL((k_xmac_ringm<MPV, false>), grid, block, 0, s, job, spec, vacc, nf, \
+                       fps, slot_stride, nullptr, 0);                                     \
+    break;
+  switch (Mp) {
+    XMAC_RINGM(4) XMAC_RINGM(8) XMAC_RINGM(12) XMAC_RINGM(16) XMAC_RINGM(20) XMAC_RINGM(24)
+    XMAC_RINGM(28) XMAC_RINGM(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef XMAC_RINGM
+  return hipGetLastError();
+}
+
+// Fused batches: the ring-fed matrix-core kernel, one workgroup per channel
+// tile, subband and frame slice of each item.
+int xmac_fused_blocks(int M, int n_chan, int n_subbands, int n_splits) {
+  (void)M;
+  return n_chan / 64 * n_subbands * n_splits;
+}
+
+hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_blocks,
+                             hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  if (Mp > 32 || Mp % kGroup != 0) return hipErrorInvalidValue;
+  const dim3 grid(n_blocks), block(256 * ringm_parts(Mp));
+#define XMAC_FUSED(MPV)                                                                   \
+  case MPV:                                                                               \
+    hipLaunchKernelGGL((k_xmac_ringm<MPV, true>), grid, block, 0, s, nullptr, nullptr,    \
+                       nullptr, 0, 0, 0, items, n_items);                                 \
+    break;
+  switch (Mp) {
+    XMAC_FUSED(4) XMAC_FUSED(8) XMAC_FUSED(12) XMAC_FUSED(16) XMAC_FUSED(20) XMAC_FUSED(24)
+    XMAC_FUSED(28) XMAC_FUSED(32)
+    default: return hipErrorInvalidValue;
+  }
+#undef XMAC_FUSED
+  return hipGetLastError();
+}
+
 static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subbands,
                                 const float2* spec, double2* vacc, size_t slot_stride, int nf,
                                 int fps_max, int kc_req, int tpw_req, hipStream_t s) {
@@ -737,20 +938,18 @@ static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subb
 
 int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands) {
   // Longer slices cut the FP64 slot traffic (one read and write of the slot
-  // per slice).  1024-frame slices where the ring's workgroups still give at
-  // least three waves per SIMD (C2: X stage 16.2 -> 15.6 ms per step; whole
-  // 2048-frame blocks leave half the CUs idle: 24.4 ms); else 512-frame
-  // slices where the 64-channel tiles give at least 512 workgroups (two per
-  // compute unit); else 256.
+  // per slice).  1024-frame slices where the ring-fed matrix kernel's
+  // workgroups still give at least three waves per SIMD (C2 with the vector
+  // ring: X stage 16.2 -> 15.6 ms per step; whole 2048-frame blocks leave
+  // half the CUs idle: 24.4 ms); else 512-frame slices where the 64-channel
+  // tiles give at least 512 workgroups (two per compute unit); else 256.
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
   const long zchunks = (ntiles + 15) / 16;
   if (Mp <= 32 && n_chan % 64 == 0) {
-    int tpw, zc, waves;
-    ring_shape(Mp, tpw, zc, waves);
-    const long wgs1k = (long)(n_chan / 64) * n_subbands * zc * ((T + 1023) / 1024);
-    if (wgs1k * waves >= 3L * 1024) return 1024;
+    const long wgs1k = (long)(n_chan / 64) * n_subbands * ((T + 1023) / 1024);
+    if (wgs1k * 4 * ringm_parts(Mp) >= 3L * 1024) return 1024;
   }
   const long wgs = (long)(n_chan / 64) * n_subbands * zchunks * ((T + 511) / 512);
   return wgs >= 512 ? 512 : 256;
@@ -821,15 +1020,15 @@ hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
                        int fb, int kc, int tpw, hipStream_t s) {
   if (fps < 1) return hipErrorInvalidValue;
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
-  // default: the matrix cores where the vector ring would need two or three
-  // workgroups (each loading every input) per channel tile and the matrix
-  // cores measured faster (24 inputs: 0.82 vs 1.12 ms, 32: 1.70 vs 2.16 ms on
-  // C4-shaped jobs of 1024 frames; 28 inputs, where the matrix stage needs two
-  // waves per channel block, 1.47 vs 1.29 ms), else the ring
-  if (fb == 0 && (Mp == 24 || Mp == 32) && kc == 0 && tpw == 0 && n_chan % 16 == 0)
-    fb = kXmacMatrix;
+  // default up to 32 inputs: the matrix cores fed through the LDS ring
+  // (C4-shaped jobs of 1024 frames, against the vector ring: 32 inputs 0.76
+  // vs 2.08 ms, 24: 0.57 vs 1.06, 20: 0.475 vs 0.485, 4: 0.086 vs 0.097, 8
+  // and 16 equal within 2 %; the vector units are left free)
+  if (fb == 0 && Mp <= 32 && kc == 0 && tpw == 0 && n_chan % 64 == 0) fb = kXmacMatrixRing;
   if ((fb == 0 || fb == kRing) && Mp <= 32 && (kc == 0 || kc == 64))
     return launch_ring(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, tpw, s);
+  if (fb == kXmacMatrixRing && Mp <= 32 && n_chan % 64 == 0)
+    return launch_ringm(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, s);
   if (fb == kXmacMatrix && Mp <= 32 && n_chan % 16 == 0)
     return launch_mfma(job, M, n_chan, n_subbands, spec, vacc, slot_stride, nf, fps, s);
   if (fb == 1)

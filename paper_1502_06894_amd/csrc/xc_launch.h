@@ -35,8 +35,8 @@ struct FusedItem {
 };
 
 // The item whose numbers start at or before `x` (first[i] ascending, first[0] = 0).
-template <class Get>
-__device__ inline int fused_find(const FusedItem* items, int n, int x, Get first) {
+template <class P, class Get>
+__device__ inline int fused_find(P items, int n, int x, Get first) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -154,10 +154,13 @@ int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands);
 // A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
 // (double2), slot_stride elements apart; fps: xmac_frames_per_split of the job.
 // fb: staging (8 = LDS ring, 2 or 4 = register-staged stages, 1 = none,
-// kXmacMatrix = FP32 products on the matrix cores, 0 = default); kc: channel
+// kXmacMatrix = FP32 products on the matrix cores with operands loaded per
+// wave, kXmacMatrixRing = the same products fed through the LDS ring, 0 =
+// default); kc: channel
 // tile (16/32/64, 0 = auto); tpw: 4x4 tiles per workgroup (0 = all that fit).
 // Every staging gives bit-identical sums.
 constexpr int kXmacMatrix = 3;
+constexpr int kXmacMatrixRing = 5;
 hipError_t launch_xmac(const DevJob* job, int M, int n_chan, int n_subbands,
                        const float2* spec, double2* vacc, size_t slot_stride, int nf, int fps,
                        int fb, int kc, int tpw, hipStream_t s);
@@ -188,7 +191,8 @@ int fstage_fused_tasks(int N, int waves, int n_stations, int n_inputs, int nf);
 // The F-stage variant of a fused batch item: what the per-job path would run.
 int fstage_fused_variant(int N, int n_pols, int n_chan);
 // X stage over every item (all with inputs padded to Mp = MP, 64-channel tiles:
-// the LDS-ring kernel); workgroups of one item: xmac_fused_blocks.
+// the matrix cores fed through the LDS ring); workgroups of one item:
+// xmac_fused_blocks.
 hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_blocks,
                              hipStream_t s);
 int xmac_fused_blocks(int M, int n_chan, int n_subbands, int n_splits);

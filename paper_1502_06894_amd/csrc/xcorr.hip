@@ -662,7 +662,7 @@ int xc_set_tuning(xc_ctx* c, const xc_tuning* t) {
                    t->fstage_waves_per_simd == kFstageLean) &&
                   (t->xmac_frames_per_stage == 0 || t->xmac_frames_per_stage == 1 ||
                    t->xmac_frames_per_stage == 2 || t->xmac_frames_per_stage == kXmacMatrix ||
-                   t->xmac_frames_per_stage == 4 || t->xmac_frames_per_stage == 8) &&
+                   t->xmac_frames_per_stage == 4 || t->xmac_frames_per_stage == kXmacMatrixRing || t->xmac_frames_per_stage == 8) &&
                   (t->xmac_channels_per_wg == 0 || t->xmac_channels_per_wg == 16 ||
                    t->xmac_channels_per_wg == 32 || t->xmac_channels_per_wg == 64) &&
                   t->frames_per_block >= 0 && t->frames_per_block <= kMaxBlockFrames &&

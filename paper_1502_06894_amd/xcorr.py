@@ -52,6 +52,8 @@ XC_BATCH_GRAPH = 1
 XC_BATCH_LANES = 2
 # xc_tuning.xmac_frames_per_stage: FP32 products on the matrix cores
 XMAC_MATRIX = 3
+# ... the same products fed through the LDS ring
+XMAC_MATRIX_RING = 5
 
 
 class XcTuning(C.Structure):

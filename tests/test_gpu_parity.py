@@ -395,19 +395,22 @@ MATRIX_CASES = [
 ]
 
 
+@pytest.mark.parametrize("staging", ["matrix", "matrix_ring"])
 @pytest.mark.parametrize("name,kw,fpb", MATRIX_CASES, ids=[c[0] for c in MATRIX_CASES])
-def test_matrix_core_x_stage(xc, corr, name, kw, fpb):
-    """FP32 X stage on the matrix cores: each 4x4x1 block element is a fused
+def test_matrix_core_x_stage(xc, corr, name, kw, fpb, staging):
+    """FP32 X stage on the matrix cores, operands loaded per wave (matrix) or
+    fed through the LDS ring (matrix_ring): each 4x4x1 block element is a fused
     multiply-add with one rounding, issued in the vector kernels' order, so the
-    visibilities equal the vector X stage's bit for bit (and the oracle's within
+    visibilities equal the vector ring's bit for bit (and the oracle's within
     the FP32 tolerance)."""
     job = configs.small_job(**kw, seed=zlib.crc32(name.encode()) % 1000)
     V, W = fx.correlate(job, threads=8)
     _on_gpu(xc, job)
+    fb = {"matrix": xc.XMAC_MATRIX, "matrix_ring": xc.XMAC_MATRIX_RING}[staging]
     try:
-        corr.set_tuning(xmac_frames_per_stage=0)
+        corr.set_tuning(xmac_frames_per_stage=8)   # the vector ring
         vec, w0 = corr.correlate(job, frames_per_block=fpb)
-        corr.set_tuning(xmac_frames_per_stage=xc.XMAC_MATRIX)
+        corr.set_tuning(xmac_frames_per_stage=fb)
         mat, w1 = corr.correlate(job, frames_per_block=fpb)
         torch.cuda.synchronize()
     finally:
@@ -433,6 +436,7 @@ def test_tuning_variants_bit_identical(xc, corr):
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=1),
                      dict(xmac_frames_per_stage=1, xmac_tiles_per_wg=3, xmac_channels_per_wg=16),
                      dict(xmac_frames_per_stage=3),
+                     dict(xmac_frames_per_stage=5),
                      dict(fstage_waves_per_simd=1), dict(fstage_waves_per_simd=2),
                      dict(fstage_waves_per_simd=3),
                      dict(fstage_waves_per_simd=4), dict(fstage_waves_per_simd=8)]:
