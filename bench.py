@@ -279,15 +279,17 @@ def _counter_means(db_path: str, counter: str) -> dict:
 # The C2 workload's F and X kernels in a counter database: the F-stage and
 # X-stage kernels of its FFT length and input count, whatever variant the
 # library's defaults pick (the one with the most dispatches).
-C2_KERNELS = {"fstage": ("xc::k_fstage<2048,", F_SOURCES), "xmac": ("xc::k_xmac_ring<20,", X_SOURCES)}
+C2_KERNELS = {"fstage": (("xc::k_fstage<2048,",), F_SOURCES),
+              "xmac": (("xc::k_xmac_ringm<20,", "xc::k_xmac_ring<20,", "xc::k_xmac_mfma<5,"),
+                       X_SOURCES)}
 
 
 def _resolve_kernels(counts: dict, kernels: dict) -> dict:
     out = {}
-    for kind, (prefix, srcs) in kernels.items():
-        names = [n for n in counts if n.startswith(prefix)]
+    for kind, (prefixes, srcs) in kernels.items():
+        names = [n for n in counts if n.startswith(prefixes)]
         if not names:
-            raise SystemExit(f"no kernel {prefix}... in the counter database")
+            raise SystemExit(f"no kernel {' / '.join(prefixes)}... in the counter database")
         out[kind] = (max(names, key=lambda n: counts[n]), srcs)
     return out
 
