@@ -139,6 +139,8 @@ def roofline(kind: str, bytes_per_ss: float, flops_per_ss: float, src_files, pro
                 "peak_at_2p4_ghz": round(VALU_ISSUE_PEAK_T, 2),
                 "frac": round(rate / VALU_ISSUE_PEAK_T, 4),
                 "valu_busy_counter": round(v["valu_busy"], 3)}
+        if "mfma_busy" in v:
+            valu["mfma_busy_counter"] = round(v["mfma_busy"], 3)
     return {"bound": bound, "achieved": main["achieved"], "peak": main["peak"],
             "unit": main["unit"], "frac": main["frac"],
             "traffic": None if tr is None else round(tr * ss_launch),
@@ -306,17 +308,22 @@ def _dispatch_counts(db_path: str, counter: str) -> dict:
 
 
 def valu_json(db: str, ss_per_launch: float, kernels: dict) -> dict:
-    """VALU instructions per station-sample (SQ_INSTS_VALU x 64 / ss) and VALU
-    busy (SQ_ACTIVE_INST_VALU / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs)) per kernel kind."""
+    """VALU instructions per station-sample (SQ_INSTS_VALU x 64 / ss), VALU
+    busy (SQ_ACTIVE_INST_VALU / (256 CUs x GRBM_GUI_ACTIVE / 8 XCDs)) and, where
+    the run also counted SQ_VALU_MFMA_BUSY_CYCLES, matrix-core busy per kernel kind."""
     insts = _counter_means(db, "SQ_INSTS_VALU")
     active = _counter_means(db, "SQ_ACTIVE_INST_VALU")
     grbm = _counter_means(db, "GRBM_GUI_ACTIVE")
+    mfma = _counter_means(db, "SQ_VALU_MFMA_BUSY_CYCLES")
     kernels = _resolve_kernels(_dispatch_counts(db, "SQ_INSTS_VALU"), kernels)
     out = {"ss_per_launch": ss_per_launch}
     for kind, (name, srcs) in kernels.items():
         out[kind] = {"kernel": name, "source_hash": kernel_source_hash(srcs),
                      "instr_per_station_sample": insts[name] * 64.0 / ss_per_launch,
                      "valu_busy": active[name] / (256.0 * grbm[name] / 8.0)}
+        if name in mfma:
+            # matrix-core busy cycles over 1024 SIMDs x the cycles of one XCD
+            out[kind]["mfma_busy"] = mfma[name] / (1024.0 * grbm[name] / 8.0)
     return out
 
 
@@ -1006,6 +1013,9 @@ def main():
               "xmac": (4.0, 2.0 * (job.M + 1), X_SOURCES)}
     dom = max(per_ss, key=lambda k: prof[k][0])
     roof = roofline(dom, *per_ss[dom], prof[dom], ss * a.steps)
+    # the other stage's record beside it (same fields)
+    roof["other_stage"] = {k: roofline(k, *per_ss[k], prof[k], ss * a.steps)
+                           for k in per_ss if k != dom and prof[k][1]}
     # the whole staged path against HBM: every station-sample moves 8.25 B
     roof["path_hbm"] = {"achieved": round(8.25 * value, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(8.25 * value / HBM_PEAK_GBS, 4),
