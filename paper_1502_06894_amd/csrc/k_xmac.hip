@@ -653,9 +653,12 @@ static hipError_t launch_mfma(const DevJob* job, int M, int n_chan, int n_subban
 // q * kRingmQuad + x * kRingmPair of a stage, so row 4g + r of every group
 // g starts 64 r bytes into a 256-byte bank window: the 32 lanes of a half-wave
 // (8 channels x 4 rows) read 32 different 8-byte bank pairs of the 64 banks.
-// A last, half-filled quad (MP % 8 == 4) loads its rows again into the unused
-// halves.  Products are issued in the vector kernels' order, so the sums are
-// bit-identical to theirs.
+// (The compiler pairs two groups' reads, a multiple of 512 bytes apart, into
+// one read2st64, whose two addresses of a lane then share a bank; the counters
+// show those conflicts, and a layout that prevents the pairing measured no
+// faster.)  A last, half-filled quad (MP % 8 == 4) loads its rows again into
+// the unused halves.  Products are issued in the vector kernels' order, so the
+// sums are bit-identical to theirs.
 constexpr int kRingmPair = 1024 + 64;   // bytes: 64 r mod 256 for the pair at x = r
 // bytes per quad: a multiple of 512 (one LDS base register serves every row of
 // a stage: read2st64 offsets count 512-byte units)
