@@ -731,6 +731,47 @@ def run_xcross(a):
             "rows": rows}
 
 
+def run_fstage_n(a):
+    """F- and X-stage throughput by FFT length: single-pol jobs of 12 stations x 4
+    subbands (64 Msps), 2^25 samples per input, N = 256 .. 32768, the library's
+    default variants; kernel time per call from HIP events."""
+    import torch
+    from paper_1502_06894_amd import xcorr
+    from synth import configs
+    corr = _correlator(a)
+    rows = []
+    for n_chan in (128, 256, 512, 1024, 2048, 4096, 8192, 16384):
+        N = 2 * n_chan
+        job = configs.c4_job(device="cuda", n_stations=12, n_subbands=4, n_chan=n_chan,
+                             n_frames=(1 << 25) // N)
+        xcorr.job_to_device(job, "cuda:0")
+        ws = corr.alloc_workspace(job)
+        out = corr.alloc_output(job)
+        for _ in range(a.warmup):
+            corr.correlate(job, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        corr.profile_begin(a.steps * 64 + 64)
+        for _ in range(a.steps):
+            corr.correlate(job, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        prof = corr.profile_end()
+        ss = job.station_samples
+        f_ms, x_ms = prof["fstage"][0] / a.steps, prof["xmac"][0] / a.steps
+        rows.append({"fft_len": N, "station_samples": ss, "f_ms": round(f_ms, 4),
+                     "f_gss_per_s": round(ss / f_ms / 1e6, 1), "x_ms": round(x_ms, 4),
+                     "x_gss_per_s": round(ss / x_ms / 1e6, 1)})
+        log(f"N = {N:5d}: F {f_ms:.3f} ms ({ss / f_ms / 1e6:.1f} G ss/s), "
+            f"X {x_ms:.3f} ms ({ss / x_ms / 1e6:.1f} G ss/s)")
+        del ws, out, job
+        torch.cuda.empty_cache()
+    return {"metric": "F- and X-stage station-samples/s by FFT length", "value": None,
+            "unit": "G station-samples/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "higher_is_better": True, "data": "synthetic", "dtype": "f32",
+            "config": {"workload": "single-pol jobs: 12 stations x 4 subbands at 64 Msps, "
+                                   "2^25 samples per input, N = 256..32768"},
+            "rows": rows}
+
+
 def run_fringe(a):
     """Delay-rate fringe search over a scan of C2-shaped visibilities: T = 64
     sub-integrations x 8 subbands x 210 baselines x 1024 channels, delay
@@ -941,9 +982,9 @@ def main():
         calibrate_read()
         return
 
-    if a.workload in ("c3", "c4", "c5", "fringe", "feed", "xcross"):
+    if a.workload in ("c3", "c4", "c5", "fringe", "feed", "xcross", "fstage-n"):
         res = {"c3": run_c3, "c4": run_c4, "c5": run_c5, "fringe": run_fringe,
-               "feed": run_feed, "xcross": run_xcross}[a.workload](a)
+               "feed": run_feed, "xcross": run_xcross, "fstage-n": run_fstage_n}[a.workload](a)
         print(json.dumps(res), flush=True)
         return
 
