@@ -383,6 +383,7 @@ MATRIX_CASES = [
     # (one and two tile parts per channel block), ragged frame counts and
     # several slots
     ("mg1", dict(n_stations=2, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=9), 0),
+    ("one_input", dict(n_stations=1, n_subbands=1, n_pols=1, n_chan=256, C=1, n_frames=11), 0),
     ("mg2", dict(n_stations=3, n_subbands=1, n_pols=2, n_chan=256, C=2, n_frames=23), 0),
     ("mg3", dict(n_stations=6, n_subbands=2, n_pols=2, n_chan=128, C=4, n_frames=41), 0),
     ("mg4", dict(n_stations=16, n_subbands=1, n_pols=1, n_chan=128, C=1, n_frames=13), 0),
