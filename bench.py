@@ -1061,6 +1061,11 @@ def main():
     roof["path_hbm"] = {"achieved": round(8.25 * value, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(8.25 * value / HBM_PEAK_GBS, 4),
                         "bytes_per_station_sample": 8.25}
+    # the algorithmic figure of a fully fused path: only the 2-bit input (0.25 B
+    # per station-sample) has to cross HBM
+    roof["input_only_hbm"] = {"achieved": round(0.25 * value, 1), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(0.25 * value / HBM_PEAK_GBS, 4),
+                              "bytes_per_station_sample": 0.25}
     kernels = {k: {"ms_per_step": round(ms / a.steps, 3), "launches_per_step": n // a.steps}
                for k, (ms, n) in prof.items() if n}
 
