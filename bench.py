@@ -13,7 +13,8 @@ Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py --workload c5        # Poisson request trace through the server
   python bench.py --workload fringe    # delay-rate fringe search over a C2-shaped scan
   python bench.py --workload feed      # feed-angle correction over a C2-shaped scan
-  python bench.py --workload xcross    # X stage: vector FP32 vs MFMA FP16 / e4m3 as inputs grow
+  python bench.py --workload xcross    # X stage: vector and matrix-core FP32, MFMA FP16 / e4m3 as inputs grow
+  python bench.py --workload fstage-n  # F and X stage throughput by FFT length (single-pol jobs)
   python bench.py --calibrate-copy     # plain device copy of known size, for counter scaling
   python bench.py --rocpd-summary DB   # per-kernel table from a rocprofv3 database
 """
