@@ -381,9 +381,9 @@ def calibrate_copy():
 
 def _default_fpb(job, elem_bytes=8):
     """The library's default frames per block: 2048, or up to 65536 while the
-    block's staged spectra stay within 256 MiB."""
+    block's staged spectra stay within 16 GiB."""
     per_frame = job.n_subbands * job.M * job.n_chan * elem_bytes
-    return int(min(max(2048, min(65536, (256 << 20) // per_frame)), job.n_frames))
+    return int(min(max(2048, min(65536, (16 << 30) // per_frame)), job.n_frames))
 
 
 def _batch_fpb(job, tuned_fpb=0, elem_bytes=8):
@@ -940,9 +940,10 @@ def main():
     ap.add_argument("--valu-json", metavar="VALU_DB",
                     help="write profiles/valu_counters.json from an SQ_INSTS_VALU + "
                          "SQ_ACTIVE_INST_VALU + GRBM_GUI_ACTIVE run of the C2 workload, and exit")
-    ap.add_argument("--ss-per-launch", type=float, default=671088640.0,
-                    help="--traffic-json: station-samples per F / X launch of the profiled run "
-                         "(C2: 10 stations x 16 inputs x 2048 frames x 2048 samples)")
+    ap.add_argument("--ss-per-launch", type=float, default=4295032832.0,
+                    help="--traffic-json / --valu-json: station-samples per F / X launch of the "
+                         "profiled run (C2 with --frames 13107, one default block: 10 stations x "
+                         "16 inputs x 13107 frames x 2048 samples)")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
                     help="c4: precision reported as the value")
     ap.add_argument("--jobs", type=int, default=64, help="c3: number of jobs")

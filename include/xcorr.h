@@ -99,8 +99,9 @@ typedef struct {
   int32_t precision;           /* XC_FP32 | XC_FP16_MFMA | XC_FP8_MFMA */
   int32_t frames_per_block;    /* frames staged per F/X round, at most 65536; 0 = library
                                   default: 2048, or more (up to 65536) while the block's
-                                  staged spectra stay within 256 MiB, so that small jobs
-                                  run in fewer, larger rounds */
+                                  staged spectra stay within 16 GiB, so that a job runs
+                                  in few, large rounds (the workspace grows with it:
+                                  xc_workspace_bytes) */
 } xc_setup;
 
 typedef struct {

@@ -23,9 +23,13 @@ constexpr size_t kSlotBytes = 256 * 1024;
 constexpr size_t kAlign = 256;
 constexpr int kMaxBlockFrames = 65536;
 // Default frames per block: 2048, or more while the block's staged spectra
-// stay within kDefaultBlockBytes (small jobs run in fewer, larger rounds).
+// stay within kDefaultBlockBytes.  A job alone on the device then runs in a
+// few large rounds (a C2 sub-integration in 5 instead of 31): every round
+// costs each kernel's ramp-up and drain and the X stage one read-modify-write
+// of the FP64 accumulator slots, and a 16 GiB block is 6 % of the HBM.  Jobs
+// that share the device (batches, served requests) cap their blocks lower.
 constexpr int kDefaultBlockFrames = 2048;
-constexpr size_t kDefaultBlockBytes = (size_t)256 << 20;
+constexpr size_t kDefaultBlockBytes = (size_t)16 << 30;
 constexpr int kScaleFrames = 64;          // frames that set the MFMA path's channel scales
 constexpr int kF16TargetLog2 = 10;        // FP16: scaled RMS 2^10 (max 65504)
 constexpr int kF8TargetLog2 = 5;          // e4m3: scaled RMS 2^5 (max 448)

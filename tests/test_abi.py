@@ -115,7 +115,7 @@ def test_workspace_bytes_and_validation_on_host():
         sb, stb, kb = _setup(**bad)
         assert lib.xc_workspace_bytes(None, C.byref(sb), stb) == 0, bad
     # the default block of a small job: past 2048 frames while its spectra stay
-    # within 256 MiB (here the whole 10000-frame job in one block)
+    # within 16 GiB (here the whole 10000-frame job in one block)
     s4, st4, k4 = _setup(n_frames=10000)
     s5, st5, k5 = _setup(n_frames=10000, frames_per_block=2048)
     s6, st6, k6 = _setup(n_frames=10000, frames_per_block=10000)
