@@ -10,6 +10,7 @@ Prints one JSON line (stdout).  Progress goes to stderr.
   python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--no-cpu-baseline]
   python bench.py --workload c4 --precision fp16|fp8|fp32   # X stage on MFMA (FP16/FP8) or FP32
   python bench.py --workload c3        # 64 uneven jobs: batch (lanes + hipGraph) vs per-job loop
+  python bench.py --workload c3 --job-mix short --no-autotune   # 256 short jobs, the same comparison
   python bench.py --workload c5        # Poisson request trace through the server
   python bench.py --workload fringe    # delay-rate fringe search over a C2-shaped scan
   python bench.py --workload feed      # feed-angle correction over a C2-shaped scan
@@ -388,9 +389,14 @@ def _default_fpb(job, elem_bytes=8):
 
 def _batch_fpb(job, tuned_fpb=0, elem_bytes=8):
     """Frames per block a batch gives a job: the tuned size (else the library
-    default), capped as for every job sharing the device (1 GiB, at least 64)."""
+    default), capped as for every job sharing the device (1 GiB, at least 64),
+    except that a job the cap would cut into more than 4 blocks keeps the
+    uncapped size (it runs alone on the batch's first lane)."""
     T = min(tuned_fpb, job.n_frames) if tuned_fpb else _default_fpb(job, elem_bytes)
-    return _shared_fpb(job, T, 1 << 30, 64, elem_bytes)
+    t = _shared_fpb(job, T, 1 << 30, 64, elem_bytes)
+    if t != T and -(-job.n_frames // t) > 4:
+        return int(T)
+    return t
 
 
 # X-stage staging values of the library's tuning record, by name
@@ -407,7 +413,9 @@ def run_c3(a):
     from synth import configs
     log("generating the 20-station x 16-stream x 4.5 s pool on the GPU")
     pool = configs.pool_recordings(device="cuda")
-    jobs = configs.batch_jobs(pool, a.jobs)
+    short = a.job_mix == "short"
+    jobs = (configs.short_batch_jobs(pool, a.jobs or 256) if short
+            else configs.batch_jobs(pool, a.jobs or 64))
     torch.cuda.synchronize()
     ss = sum(j.station_samples for j in jobs)
     log(f"{len(jobs)} jobs, {ss:.3e} station-samples")
@@ -449,6 +457,24 @@ def run_c3(a):
     log(f"per-job loop: {t_loop * 1e3:.1f} ms per batch, {ss / t_loop / 1e9:.1f} G ss/s")
     refs = [(v.clone(), w.clone()) for v, w in outs]
     del ws
+    # the plain per-job path a caller gets without choosing block sizes: the
+    # library's default blocks (up to 16 GiB of spectra; the tuned size where
+    # the autotuner picked one)
+    dfl = [t.get("frames_per_block", 0) for t in tuned]
+    ws = torch.empty(max(corr.workspace_bytes(j, frames_per_block=f) for j, f in zip(jobs, dfl)),
+                     dtype=torch.uint8, device="cuda")
+    for j, f, o in zip(jobs, dfl, outs):
+        corr.correlate(j, frames_per_block=f, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        for j, f, o in zip(jobs, dfl, outs):
+            corr.correlate(j, frames_per_block=f, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    t_dfl = (time.perf_counter() - t0) / a.steps
+    log(f"per-job loop at the library's default blocks: {t_dfl * 1e3:.1f} ms per batch, "
+        f"{ss / t_dfl / 1e9:.1f} G ss/s")
+    del ws
     lanes = a.lanes or 8
     res = {}
     for name, lanes_only in (("lanes", True), ("fused", False)):
@@ -470,10 +496,13 @@ def run_c3(a):
         same = all(torch.equal(v, rv) and torch.equal(w, rw)
                    for (v, w), (rv, rw) in zip(bouts, refs))
         res[name] = {"value": round(ss / tb / 1e9, 2), "ms_per_step": round(tb * 1e3, 3),
-                     "over_per_job_loop": round(t_loop / tb, 3), "identical_to_per_job": bool(same),
+                     "over_per_job_loop": round(t_loop / tb, 3),
+                     "over_per_job_default_blocks": round(t_dfl / tb, 3),
+                     "identical_to_per_job": bool(same),
                      "workspace_gb": round(bws.numel() / 1e9, 2)}
         log(f"batch {name} ({lanes} lanes, graph replay): {tb * 1e3:.1f} ms, "
-            f"{ss / tb / 1e9:.1f} G ss/s ({t_loop / tb:.3f}x the per-job loop); identical: {same}")
+            f"{ss / tb / 1e9:.1f} G ss/s ({t_loop / tb:.3f}x the per-job loop, "
+            f"{t_dfl / tb:.3f}x at default blocks); identical: {same}")
         del bws, bouts
         torch.cuda.synchronize()
     f = res["fused"]
@@ -482,12 +511,18 @@ def run_c3(a):
         "unit": "G station-samples/s", "n_gpus": 1, "steps": a.steps, "warmup": 1,
         "ms_per_step": f["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"C3: {len(jobs)} uneven sub-integration jobs (stations 2-20, "
-                               f"subbands 1-16, channels 128-8192, 0.1-4 s) over a 20-station "
-                               f"x 16-stream x 4.5 s device-resident pool",
+        "config": {"workload": (f"{len(jobs)} short sub-integration jobs (stations 2-6, subbands "
+                                f"1-4, channels 128-1024, 0.01-0.1 s) over a 20-station x "
+                                f"16-stream x 4.5 s device-resident pool" if short else
+                                f"C3: {len(jobs)} uneven sub-integration jobs (stations 2-20, "
+                                f"subbands 1-16, channels 128-8192, 0.1-4 s) over a 20-station "
+                                f"x 16-stream x 4.5 s device-resident pool"),
                    "lanes": lanes, "graph": True, "station_samples_per_step": ss,
                    "autotuned": not a.no_autotune},
-        "per_job_loop": {"value": round(ss / t_loop / 1e9, 2), "ms_per_step": round(t_loop * 1e3, 3)},
+        "per_job_loop": {"value": round(ss / t_loop / 1e9, 2), "ms_per_step": round(t_loop * 1e3, 3),
+                         "blocks": "the batch's"},
+        "per_job_loop_default_blocks": {"value": round(ss / t_dfl / 1e9, 2),
+                                        "ms_per_step": round(t_dfl * 1e3, 3)},
         "fused": f, "lanes": res["lanes"],
         "batch_over_loop": f["over_per_job_loop"],
         "identical_to_per_job": f["identical_to_per_job"] and res["lanes"]["identical_to_per_job"],
@@ -568,9 +603,11 @@ def _shared_fpb(job, T, cap, min_frames, elem_bytes=8):
     return int(min(t, T))
 
 
-def _server_fpb(job, elem_bytes=8):
-    """Frames per block the server gives a request (1 GiB cap, at least 16 frames)."""
-    return _shared_fpb(job, _default_fpb(job, elem_bytes), 1 << 30, 16, elem_bytes)
+def _server_fpb(job, budget, slots, elem_bytes=8):
+    """Frames per block the server gives a request: its spectra capped at half
+    the budget shared among the slots (at least 1 GiB), at least 16 frames."""
+    cap = max(1 << 30, budget // (2 * slots))
+    return _shared_fpb(job, _default_fpb(job, elem_bytes), cap, 16, elem_bytes)
 
 
 def run_c5(a):
@@ -643,7 +680,7 @@ def run_c5(a):
     same = 0
     for i in idx:
         j = jobs[i]
-        v, w = corr.correlate(j, frames_per_block=_server_fpb(j))
+        v, w = corr.correlate(j, frames_per_block=_server_fpb(j, a.budget_gb << 30, slots))
         same += int(torch.equal(v, outs[i][0]) and torch.equal(w, outs[i][1]))
     torch.cuda.synchronize()
     log(f"alone == in the mix, bit for bit: {same} of {n_check} sampled requests")
@@ -946,7 +983,9 @@ def main():
                          "16 inputs x 13107 frames x 2048 samples)")
     ap.add_argument("--precision", default="fp16", choices=["fp32", "fp16", "fp8"],
                     help="c4: precision reported as the value")
-    ap.add_argument("--jobs", type=int, default=64, help="c3: number of jobs")
+    ap.add_argument("--jobs", type=int, default=0, help="c3: number of jobs (64; 256 short)")
+    ap.add_argument("--job-mix", default="c3", choices=["c3", "short"],
+                    help="c3: the C3 mix, or many short jobs (the regime batching is for)")
     ap.add_argument("--no-autotune", action="store_true", help="c3: library default tile shapes")
     ap.add_argument("--lanes", type=int, default=0,
                     help="c3: concurrent lanes (default 8); c5: server slots (default 16)")

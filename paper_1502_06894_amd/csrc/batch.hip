@@ -10,6 +10,11 @@ using namespace xc;
 namespace {
 
 constexpr size_t kBatchSpecCap = (size_t)1 << 30;   // per-job staged spectra in a batch
+// Jobs of more blocks than this run as single jobs: their own launches already
+// fill the GPU block after block, and in rounds they would hold their group's
+// lane for as many rounds as they have blocks.  Fusing pays for the short jobs,
+// whose launches are too small to fill the GPU alone.
+constexpr int kFusedMaxBlocks = 4;
 constexpr int64_t kTuneFrames = 8192;               // frames an autotune candidate runs
 
 struct Plan {
@@ -20,6 +25,7 @@ struct Plan {
   std::vector<int> lane_of;
   std::vector<std::vector<int>> order;   // per lane: jobs in launch order
   std::vector<size_t> arena_off;         // per lane
+  std::vector<char> solo;                // per job: long, at the library's block size, lane 0
   size_t desc_bytes = 0, total = 0;
 };
 
@@ -35,6 +41,7 @@ int plan_batch(xc_ctx* c, const xc_job* jobs, int n, int lanes, Plan& P) {
   P.layouts.resize(n);
   P.desc_off.resize(n);
   P.lane_of.assign(n, 0);
+  P.solo.assign(n, 0);
   for (int j = 0; j < n; ++j) {
     int rc = validate(c, &jobs[j].setup, jobs[j].st);
     if (rc != XC_OK) {
@@ -46,12 +53,20 @@ int plan_batch(xc_ctx* c, const xc_job* jobs, int n, int lanes, Plan& P) {
     xc_setup s = jobs[j].setup;
     xc_tuning tu = effective_tuning(c, &s);
     Layout L = layout_of(&s, jobs[j].st, tu);
-    // bound each job's staged spectra so that many jobs fit in HBM together
+    // bound each job's staged spectra so that many jobs fit in HBM together;
+    // a job that the bound would cut into more than kFusedMaxBlocks blocks
+    // keeps the library's (larger) default block instead and runs alone on
+    // lane 0, after or before the other long jobs: it fills the GPU by itself,
+    // and its rounds cost as little as when it runs outside a batch
     if (s.frames_per_block == 0) {
       const int T = shared_block_frames(s, L, kBatchSpecCap, 64);
       if (T != L.T) {
-        s.frames_per_block = T;
-        L = layout_of(&s, jobs[j].st, tu);
+        if ((s.n_frames + T - 1) / T > kFusedMaxBlocks) {
+          P.solo[j] = 1;
+        } else {
+          s.frames_per_block = T;
+          L = layout_of(&s, jobs[j].st, tu);
+        }
       }
     }
     P.setups[j] = s;
@@ -69,8 +84,9 @@ int plan_batch(xc_ctx* c, const xc_job* jobs, int n, int lanes, Plan& P) {
   std::vector<int64_t> load(lanes, 0);
   std::vector<size_t> arena(lanes, 0);
   P.order.assign(lanes, {});
+  std::stable_partition(idx.begin(), idx.end(), [&](int j) { return P.solo[j] != 0; });
   for (int j : idx) {
-    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    const int l = P.solo[j] ? 0 : (int)(std::min_element(load.begin(), load.end()) - load.begin());
     load[l] += job_cost(P.setups[j]);
     P.lane_of[j] = l;
     P.order[l].push_back(j);
@@ -219,12 +235,6 @@ struct FPlan {
   size_t total = 0;
 };
 
-// Jobs of more blocks than this run as single jobs: their own launches already
-// fill the GPU block after block, and in rounds they would hold their group's
-// lane for as many rounds as they have blocks.  Fusing pays for the short jobs,
-// whose launches are too small to fill the GPU alone.
-constexpr int kFusedMaxBlocks = 4;
-
 bool fused_job_ok(const xc_setup& s, const xc_station* st, const xc_tuning& tu, int T) {
   const int N = 2 * s.n_chan;
   if ((s.n_frames + T - 1) / T > kFusedMaxBlocks) return false;
@@ -250,7 +260,7 @@ int plan_fused(xc_ctx* c, const xc_job* jobs, int n, int lanes, FPlan& F) {
     const xc_setup& s = P.setups[j];
     F.st[j].assign(jobs[j].st, jobs[j].st + s.n_stations);
     F.st_mask[j].assign(s.n_stations, -1);
-    if (!fused_job_ok(s, jobs[j].st, P.tunes[j], P.layouts[j].T)) continue;
+    if (P.solo[j] || !fused_job_ok(s, jobs[j].st, P.tunes[j], P.layouts[j].T)) continue;
     for (int i = 0; i < s.n_stations; ++i) {
       const xc_station& x = jobs[j].st[i];
       if (x.frame_ok) continue;
@@ -276,7 +286,7 @@ int plan_fused(xc_ctx* c, const xc_job* jobs, int n, int lanes, FPlan& F) {
   for (int j = 0; j < n; ++j) {
     const xc_setup& s = P.setups[j];
     F.L[j] = layout_of(&s, F.st[j].data(), P.tunes[j]);
-    if (!fused_job_ok(s, jobs[j].st, P.tunes[j], P.layouts[j].T)) continue;
+    if (P.solo[j] || !fused_job_ok(s, jobs[j].st, P.tunes[j], P.layouts[j].T)) continue;
     const int N = 2 * s.n_chan;
     const int W = fstage_fused_variant(N, s.n_pols, s.n_chan);
     auto key = std::make_pair(N, W);
@@ -423,15 +433,8 @@ int plan_fused(xc_ctx* c, const xc_job* jobs, int n, int lanes, FPlan& F) {
     F.blk_off[j] = off;
     off += F.L[j].drec_bytes + F.L[j].prec_bytes + F.L[j].spec_bytes;
   }
-  F.arena_off.assign(n, 0);
-  for (int j = 0; j < n; ++j) {
-    if (F.group_of[j] >= 0) continue;
-    F.L[j] = layout_of(&P.setups[j], jobs[j].st, P.tunes[j]);   // its own masks
-    F.arena_off[j] = off;
-    off += align_up(F.L[j].total);
-  }
-  F.total = off;
-  // lanes: groups and single jobs, longest first, each to the least loaded lane
+  // lanes: the solo jobs on lane 0, then groups and single jobs, longest
+  // first, each to the least loaded lane
   std::vector<std::pair<int64_t, int>> work;   // (cost, group g as -1 - g, or job j)
   for (size_t g = 0; g < F.groups.size(); ++g) work.push_back({F.groups[g].cost, -1 - (int)g});
   for (int j = 0; j < n; ++j)
@@ -440,17 +443,41 @@ int plan_fused(xc_ctx* c, const xc_job* jobs, int n, int lanes, FPlan& F) {
                    [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& b) {
                      return a.first > b.first;
                    });
+  std::stable_partition(work.begin(), work.end(), [&](const std::pair<int64_t, int>& w) {
+    return w.second >= 0 && P.solo[w.second];
+  });
   std::vector<int64_t> load(lanes, 0);
   F.lane_groups.assign(lanes, {});
   F.lane_jobs.assign(lanes, {});
+  std::vector<int> lane_of_job(n, 0);
   for (auto& w : work) {
-    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    const bool solo = w.second >= 0 && P.solo[w.second];
+    const int l = solo ? 0 : (int)(std::min_element(load.begin(), load.end()) - load.begin());
     load[l] += w.first;
-    if (w.second < 0)
+    if (w.second < 0) {
       F.lane_groups[l].push_back(-1 - w.second);
-    else
+    } else {
       F.lane_jobs[l].push_back(w.second);
+      lane_of_job[w.second] = l;
+    }
   }
+  // single jobs run one after another on their lane, so a lane's single jobs
+  // share one arena (its largest)
+  std::vector<size_t> lane_arena(lanes, 0);
+  for (int j = 0; j < n; ++j) {
+    if (F.group_of[j] >= 0) continue;
+    F.L[j] = layout_of(&P.setups[j], jobs[j].st, P.tunes[j]);   // its own masks
+    lane_arena[lane_of_job[j]] = std::max(lane_arena[lane_of_job[j]], align_up(F.L[j].total));
+  }
+  std::vector<size_t> lane_off(lanes, 0);
+  for (int l = 0; l < lanes; ++l) {
+    lane_off[l] = off;
+    off += lane_arena[l];
+  }
+  F.arena_off.assign(n, 0);
+  for (int j = 0; j < n; ++j)
+    if (F.group_of[j] < 0) F.arena_off[j] = lane_off[lane_of_job[j]];
+  F.total = off;
   return XC_OK;
 }
 

@@ -247,9 +247,11 @@ int xc_server_submit(xc_server* s, const xc_job* job, uint64_t* ticket) {
   r->tu = effective_tuning(s->ctx, &r->setup);
   r->L = layout_of(&r->setup, r->st.data(), r->tu);
   if (r->setup.frames_per_block == 0) {
-    // bound each request's staged spectra (1 GiB, or 16 (M + 1) frames where
-    // that is more) so that several fit in the budget together
-    const int T = shared_block_frames(r->setup, r->L, (size_t)1 << 30, 16);
+    // bound each request's staged spectra (half the budget shared among the
+    // slots, at least 1 GiB; or 16 (M + 1) frames where that is more) so that
+    // several fit in the budget together
+    const size_t cap = std::max((size_t)1 << 30, s->budget / (2 * (size_t)s->slots));
+    const int T = shared_block_frames(r->setup, r->L, cap, 16);
     if (T != r->L.T) {
       r->setup.frames_per_block = T;
       r->L = layout_of(&r->setup, r->st.data(), r->tu);

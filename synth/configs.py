@@ -187,6 +187,17 @@ def batch_jobs(pool, n_jobs: int = 64, seed: int | None = None,
             for _ in range(n_jobs)]
 
 
+def short_batch_jobs(pool, n_jobs: int = 256, seed: int | None = None,
+                     pool_seconds: float = POOL_SECONDS):
+    """Many short sub-integrations, each too small to fill the GPU alone:
+    stations U{2..6}, subbands U{1..4}, channels 2^U{7..10}, lengths
+    U[0.01, 0.1] s, single pol, 32 Msps."""
+    rng = np.random.default_rng(cfg_seed(3) + 2 if seed is None else seed)
+    return [_random_pool_job(rng, pool, s_range=(2, 6), sb_range=(1, 4), log2_chan=(7, 10),
+                             len_range=(0.01, 0.1), pool_seconds=pool_seconds)
+            for _ in range(n_jobs)]
+
+
 def serve_trace(pool, n_requests: int = 2000, rate_hz: float = 200.0, seed: int | None = None,
                 pool_seconds: float = POOL_SECONDS, max_log2_chan: int = 14):
     """C5: Poisson arrivals (seeded exponential gaps) of requests with stations

@@ -138,6 +138,33 @@ def test_fused_executor_corner_cases(xc, corr, fpb):
             assert rel_l2(refs[k][0].cpu().numpy(), V) < 1e-5, k
 
 
+def test_long_job_keeps_default_block(xc, corr):
+    """A job that the batch's 1 GiB bound on staged spectra would cut into more
+    than four blocks keeps the library's default block (here the whole job) and
+    runs alone on the first lane: with both executors, with and without graph
+    capture, every job of the batch equals the job run alone with the library
+    defaults, bit for bit (the long job's FP64 slot sums would differ in order
+    at the bounded block size)."""
+    big = configs.small_job("cuda", n_stations=5, n_subbands=8, n_pols=2, n_chan=1024, C=16,
+                            n_frames=6600, seed=31, realistic=True)
+    per_frame = 8 * 10 * 1024 * 8                        # FP32 spectra per frame
+    assert -(-big.n_frames // ((1 << 30) // per_frame)) == 5
+    jobs = [big] + _jobs(xc)[:5]
+    for j in jobs[1:]:
+        xc.job_to_device(j)
+    refs = [tuple(x.clone() for x in corr.correlate(j)) for j in jobs]
+    for lanes_only in (False, True):
+        ws = corr.batch_workspace(jobs, n_lanes=3, lanes_only=lanes_only)
+        for graph in (False, True):
+            outs = [corr.alloc_output(j) for j in jobs]
+            corr.correlate_batch(jobs, n_lanes=3, graph=graph, lanes_only=lanes_only, outs=outs,
+                                 workspace=ws)
+            torch.cuda.synchronize()
+            for k, ((v, w), (rv, rw)) in enumerate(zip(outs, refs)):
+                assert torch.equal(v, rv) and torch.equal(w, rw), (lanes_only, graph, k)
+        del ws
+
+
 def test_batch_against_oracle(xc, corr, batch):
     jobs, refs = batch
     for i in (0, 5, 11):
