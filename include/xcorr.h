@@ -335,14 +335,17 @@ const char* xc_server_last_error(xc_server* srv);
 void xc_server_destroy(xc_server* srv);
 
 /* ---------------------------------------------------------------- autotuner */
-/* Time candidate launch shapes (frames per block; X-stage stage depth and
- * channel tile) on this job (its first frames) and remember the fastest for
+/* Time candidate launch shapes (X-stage kernel, stage depth and channel tile;
+ * frames per block only where the default does not fit the workspace) on this
+ * job (its first 8192 frames) and remember the fastest for
  * every job of the same shape (FFT length, inputs, subbands, recorded
  * streams, precision) on this context.  Runs on `stream` and synchronises.
  * out/workspace as for xc_correlate_subint; candidates whose workspace does
- * not fit ws_bytes are skipped (frames per block: the library default, 512,
- * 1024 and 2048, or, when not even 512 fit, the largest power of two from 256
- * down to 16 that does).  The library default (the first candidate) stays
+ * not fit ws_bytes are skipped.  Frames per block: the library default (no
+ * smaller block is faster over a whole job; a short probe repeated back to
+ * back favours small ones through the cache), or, where it does not fit the
+ * workspace, the largest power of two up to 2048 that does.  The library
+ * default (the first candidate) stays
  * unless another candidate is more than 3 % faster.  best (host) may be NULL. */
 int xc_autotune(xc_ctx* ctx, const xc_setup* setup, const xc_station* st, const xc_output* out,
                 void* workspace, size_t ws_bytes, void* stream, xc_tuning* best);

@@ -240,7 +240,11 @@ bool fused_job_ok(const xc_setup& s, const xc_station* st, const xc_tuning& tu, 
   if ((s.n_frames + T - 1) / T > kFusedMaxBlocks) return false;
   if (s.precision != XC_FP32 || N > 16384 || any_rate_correct(&s, st)) return false;
   if (tu.fstage_waves_per_simd != 0 || tu.xmac_tiles_per_wg != 0) return false;
-  if (!(tu.xmac_frames_per_stage == 0 || tu.xmac_frames_per_stage == 8)) return false;
+  // the fused X stage is the matrix-core ring kernel, whose sums are bit-identical
+  // to the vector ring's: a job tuned to either (or to the default) can join
+  if (!(tu.xmac_frames_per_stage == 0 || tu.xmac_frames_per_stage == 8 ||
+        tu.xmac_frames_per_stage == kXmacMatrixRing))
+    return false;
   if (!(tu.xmac_channels_per_wg == 0 || tu.xmac_channels_per_wg == 64)) return false;
   return xmac_fused_ok(s.n_stations * s.n_pols, s.n_chan);
 }
@@ -700,25 +704,26 @@ int xc_autotune(xc_ctx* c, const xc_setup* setup, const xc_station* st, const xc
   if (s.n_frames > kTuneFrames) s.n_frames = kTuneFrames;
   s.frames_per_block = 0;
   std::vector<xc_tuning> cands;
-  // block sizes: the library default (0), 512, 1024 and 2048 frames; for a job
-  // too large for even 512 frames' layout in the workspace, the largest power
-  // of two that fits.  The first candidate is the library default throughout.
-  std::vector<int> fpbs = {0, 512, 1024, 2048};
-  {
-    auto fits = [&](int fpb) {
-      const xc_tuning tu = {0, 0, 0, fpb, 0, 1};
-      const Layout L = layout_of(&s, st, tu);
-      return align_up(L.desc_bytes) + L.total <= ws_bytes;
-    };
-    if (!fits(512)) {
-      fpbs = {0};
-      for (int fpb = 256; fpb >= 16; fpb /= 2)
-        if (fits(fpb)) {
-          fpbs.push_back(fpb);
-          break;
-        }
-    }
-  }
+  // block size: the library default.  Every block costs each kernel's ramp-up
+  // and drain, and no smaller block has been faster over a whole job; timed
+  // here, a smaller block wins only by the probe's artefacts (a 512-frame block
+  // that wins on 8192 frames runs a 4 s job in 122 blocks, the default in 5;
+  // a short job repeated back to back finds its input in the cache, which a
+  // run over many jobs does not).  Where the workspace is too small for the
+  // default, the largest power of two up to 2048 that fits is tried as well.
+  // The first candidate is the library default throughout.
+  auto fits = [&](int fpb) {
+    const xc_tuning tu = {0, 0, 0, fpb, 0, 1};
+    const Layout L = layout_of(&s, st, tu);
+    return align_up(L.desc_bytes) + L.total <= ws_bytes;
+  };
+  std::vector<int> fpbs = {0};
+  if (!fits(0))
+    for (int fpb = 2048; fpb >= 16; fpb /= 2)
+      if (fits(fpb)) {
+        fpbs.push_back(fpb);
+        break;
+      }
   for (int fpb : fpbs) {
     if (fpb > s.n_frames && fpb != 512) continue;
     if (s.precision == XC_FP32) {
