@@ -366,7 +366,7 @@ int plan_fused(xc_ctx* c, const xc_job* jobs, int n, int lanes, FPlan& F) {
         it.nf = (int)(s.n_frames - f0 < L.T ? s.n_frames - f0 : L.T);
         const int M = s.n_stations * s.n_pols;
         int n_splits = 0, fps = 0;
-        xmac_splits(it.nf, L.fps, n_splits, fps);
+        xmac_splits(it.nf, L.fps, M, s.n_chan, s.n_subbands, n_splits, fps);
         it.fps = fps;
         it.slot_stride = L.slot_stride;
         it.task0 = R.ntasks;

@@ -9,6 +9,8 @@
 // has a single owner, slots are summed in slot order by the finalise kernel,
 // so results do not depend on scheduling.  Spectra are staged through LDS a
 // few frames at a time, so every value is read from memory once.
+#include <atomic>
+
 #include "xc_launch.h"
 
 namespace xc {
@@ -424,7 +426,7 @@ static hipError_t launch_ring(const DevJob* job, int M, int n_chan, int n_subban
   const int ntiles = ng * (ng + 1) / 2;
   if (Mp > 32 || n_chan % 64 != 0) return hipErrorInvalidValue;
   int n_splits, fps;
-  xmac_splits(nf, fps_max, n_splits, fps);
+  xmac_splits(nf, fps_max, M, n_chan, n_subbands, n_splits, fps);
   int tiles_per_wg = tpw_req > 0 && tpw_req < 16 ? tpw_req : 16;
   if (tiles_per_wg > ntiles) tiles_per_wg = ntiles;
   const int zchunks = (ntiles + tiles_per_wg - 1) / tiles_per_wg;
@@ -451,8 +453,41 @@ bool xmac_fused_ok(int M, int n_chan) {
   return Mp <= 32 && n_chan % 64 == 0;
 }
 
-void xmac_splits(int nf, int fps_max, int& n_splits, int& fps) {
-  n_splits = (nf + fps_max - 1) / fps_max;
+long ringm_resident(int Mp);
+
+// Slice count for a block of nf frames: among ceil(nf / 1024) .. ceil(nf /
+// fps_max) slices, the one whose workgroups take the least time per compute
+// unit — (rounds of R resident workgroups, w per slice) x (frames per slice
+// plus the slot update, which moves the bytes of slot_frames frames of
+// spectra); the fewest slices among equals.  Without an occupancy figure
+// (R = 0), ceil(nf / fps_max).
+static int split_count(int nf, int fps_max, long w, long R, int slot_frames) {
+  const int hi = (nf + fps_max - 1) / fps_max;
+  if (R <= 0 || w <= 0) return hi;
+  int best = hi;
+  long best_cost = -1;
+  for (int n = (nf + 1023) / 1024; n <= hi; ++n) {
+    const long cost = ((n * w + R - 1) / R) * ((long)((nf + n - 1) / n) + slot_frames);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = n;
+    }
+  }
+  return best;
+}
+
+void xmac_splits(int nf, int fps_max, int M, int n_chan, int n_subbands, int& n_splits,
+                 int& fps) {
+  // by the ring-fed matrix kernel's grid (64-channel tiles, one workgroup per
+  // tile, subband and slice) for every X kernel, so that all of them slice a
+  // block alike and give the same sums; a slice's slot update reads and
+  // writes M (M + 1) / 2 FP64 products per channel, the bytes of 2 (M + 1)
+  // frames of FP32 spectra
+  const int Mp = (M + kGroup - 1) / kGroup * kGroup;
+  const bool ringm = Mp <= 32 && n_chan % 64 == 0;
+  n_splits = ringm ? split_count(nf, fps_max, (long)(n_chan / 64) * n_subbands, ringm_resident(Mp),
+                                 2 * (M + 1))
+                   : (nf + fps_max - 1) / fps_max;
   fps = (nf + n_splits - 1) / n_splits;
 }
 
@@ -623,7 +658,7 @@ static hipError_t launch_mfma(const DevJob* job, int M, int n_chan, int n_subban
   const int ng = (M + kGroup - 1) / kGroup;
   if (ng > 8 || n_chan % 16 != 0) return hipErrorInvalidValue;
   int n_splits, fps;
-  xmac_splits(nf, fps_max, n_splits, fps);
+  xmac_splits(nf, fps_max, M, n_chan, n_subbands, n_splits, fps);
   const int S = mfma_parts(ng);
   int blocks = 4 / S;   // channel blocks per workgroup
   if (blocks > n_chan / 16) blocks = n_chan / 16;
@@ -857,13 +892,45 @@ __global__ void __launch_bounds__(1024)
                            fa, fz, M, n_chan, nbl, sb, c, r, slot);
 }
 
+// Workgroups of the ring-fed matrix kernel (inputs padded to Mp) resident on
+// the current device at once: its occupancy per compute unit times the
+// compute units (0 where the device cannot be queried).  Set once per device
+// and Mp (host threads may race to store the same value).
+long ringm_resident(int Mp) {
+  static std::atomic<long> cache[64][9];
+  int dev = 0;
+  if (Mp < 4 || Mp > 32 || Mp % kGroup != 0 || hipGetDevice(&dev) != hipSuccess || dev < 0 ||
+      dev >= 64)
+    return 0;
+  long v = cache[dev][Mp / kGroup].load();
+  if (v != 0) return v > 0 ? v : 0;
+  const int threads = 256 * ringm_parts(Mp);
+  int per_cu = 0, n_cu = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define XMAC_RINGM_OCC(MPV)                                                                  \
+  case MPV:                                                                                  \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_xmac_ringm<MPV, false>, threads, \
+                                                     0);                                     \
+    break;
+  switch (Mp) {
+    XMAC_RINGM_OCC(4) XMAC_RINGM_OCC(8) XMAC_RINGM_OCC(12) XMAC_RINGM_OCC(16) XMAC_RINGM_OCC(20)
+    XMAC_RINGM_OCC(24) XMAC_RINGM_OCC(28) XMAC_RINGM_OCC(32)
+    default: break;
+  }
+#undef XMAC_RINGM_OCC
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  v = e == hipSuccess && per_cu > 0 && n_cu > 0 ? (long)per_cu * n_cu : -1;
+  cache[dev][Mp / kGroup].store(v);
+  return v > 0 ? v : 0;
+}
+
 static hipError_t launch_ringm(const DevJob* job, int M, int n_chan, int n_subbands,
                                const float2* spec, double2* vacc, size_t slot_stride, int nf,
                                int fps_max, hipStream_t s) {
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   if (Mp > 32 || n_chan % 64 != 0) return hipErrorInvalidValue;
   int n_splits, fps;
-  xmac_splits(nf, fps_max, n_splits, fps);
+  xmac_splits(nf, fps_max, M, n_chan, n_subbands, n_splits, fps);
   dim3 grid(n_chan / 64, n_subbands, n_splits);
   dim3 block(256 * ringm_parts(Mp));
 #define XMAC_RINGM(MPV)                                                                   \
@@ -912,8 +979,8 @@ static hipError_t launch_direct(const DevJob* job, int M, int n_chan, int n_subb
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
-  const int n_splits = (nf + fps_max - 1) / fps_max;
-  const int fps = (nf + n_splits - 1) / n_splits;
+  int n_splits, fps;
+  xmac_splits(nf, fps_max, M, n_chan, n_subbands, n_splits, fps);
   int KC = (kc_req == 16 || kc_req == 32 || kc_req == 64) ? kc_req : 64;
   if (KC > n_chan) KC = n_chan;
   int tiles_per_wg = tpw_req > 0 ? tpw_req : 1024 / KC;
@@ -952,7 +1019,17 @@ int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands) {
   const long zchunks = (ntiles + 15) / 16;
   if (Mp <= 32 && n_chan % 64 == 0) {
     const long wgs1k = (long)(n_chan / 64) * n_subbands * ((T + 1023) / 1024);
-    if (wgs1k * 4 * ringm_parts(Mp) >= 3L * 1024) return 1024;
+    if (wgs1k * 4 * ringm_parts(Mp) >= 3L * 1024) {
+      // slices of at most 1024 frames that fill whole rounds of resident
+      // workgroups (a C2 block of 13 107 frames: 14 slices, 7 rounds of 256,
+      // instead of 13, six and a half), up to twice ceil(T / 1024) slices
+      const long R = ringm_resident(Mp);
+      if (R <= 0) return 1024;
+      const int lo = (T + 1023) / 1024;
+      const int n = split_count(T, (T + 2 * lo - 1) / (2 * lo), (long)(n_chan / 64) * n_subbands, R,
+                                2 * (M + 1));
+      return (T + n - 1) / n;
+    }
   }
   const long wgs = (long)(n_chan / 64) * n_subbands * zchunks * ((T + 511) / 512);
   return wgs >= 512 ? 512 : 256;
@@ -965,8 +1042,8 @@ static hipError_t launch_fb(const DevJob* job, int M, int n_chan, int n_subbands
   const int Mp = (M + kGroup - 1) / kGroup * kGroup;
   const int ng = Mp / kGroup;
   const int ntiles = ng * (ng + 1) / 2;
-  const int n_splits = (nf + fps_max - 1) / fps_max;
-  const int fps = (nf + n_splits - 1) / n_splits;
+  int n_splits, fps;
+  xmac_splits(nf, fps_max, M, n_chan, n_subbands, n_splits, fps);
   auto lds_of = [&](int kc) { return 2 * (size_t)FB * Mp * (kc + 2) * sizeof(float2); };
   // widest channel tile that fits 64 KB of LDS and still gives a few
   // workgroups per compute unit; else the narrowest (unless one is requested)

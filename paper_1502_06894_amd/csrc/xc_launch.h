@@ -147,9 +147,10 @@ hipError_t launch_xmfma(const DevJob* job, int out, int M, int n_chan, int n_sub
                         const void* spec, const int8_t* scale_exp, double2* vacc,
                         size_t slot_stride, int nf, hipStream_t s);
 // Frames (at most) one X workgroup accumulates in FP32 before adding to its
-// FP64 slot, for blocks of T frames of a job with M inputs per subband: 1024
-// or 512 when that still gives the GPU enough workgroups, else 256.  A block
-// of nf frames uses ceil(nf / that) slots.
+// FP64 slot, for blocks of T frames of a job with M inputs per subband: up to
+// 1024 (balanced so that the ring-fed matrix kernel's workgroups fill whole
+// rounds of the GPU) or 512 when that still gives the GPU enough workgroups,
+// else 256.  A block of nf frames uses at most ceil(nf / that) slots.
 int xmac_frames_per_split(int T, int M, int n_chan, int n_subbands);
 // A6: accumulate the block's spectra into the FP64 slots vacc[split][n_sb][nbl][n_chan]
 // (double2), slot_stride elements apart; fps: xmac_frames_per_split of the job.
@@ -196,9 +197,12 @@ int fstage_fused_variant(int N, int n_pols, int n_chan);
 hipError_t launch_xmac_fused(int Mp, const FusedItem* items, int n_items, int n_blocks,
                              hipStream_t s);
 int xmac_fused_blocks(int M, int n_chan, int n_subbands, int n_splits);
-// Frame slices of a block of nf frames with at most fps_max frames each: their
-// number and the (balanced) frames per slice, as the X stage splits a block.
-void xmac_splits(int nf, int fps_max, int& n_splits, int& fps);
+// Frame slices of a block of nf frames (M inputs, n_chan channels, n_subbands)
+// with at most fps_max frames each: their number and the (balanced) frames per
+// slice, as every X kernel splits a block (where the ring-fed matrix kernel
+// takes the job, the count within ceil(nf / 1024) .. ceil(nf / fps_max) whose
+// workgroups fill the most whole rounds of the GPU).
+void xmac_splits(int nf, int fps_max, int M, int n_chan, int n_subbands, int& n_splits, int& fps);
 // Whether the fused X stage takes a job of M inputs and n_chan channels.
 bool xmac_fused_ok(int M, int n_chan);
 
