@@ -488,6 +488,7 @@ void xmac_splits(int nf, int fps_max, int M, int n_chan, int n_subbands, int& n_
   n_splits = ringm ? split_count(nf, fps_max, (long)(n_chan / 64) * n_subbands, ringm_resident(Mp),
                                  2 * (M + 1))
                    : (nf + fps_max - 1) / fps_max;
+  if (n_splits < 1) n_splits = 1;   // (an empty block: one empty slice)
   fps = (nf + n_splits - 1) / n_splits;
 }
 
