@@ -421,6 +421,27 @@ def test_matrix_core_x_stage(xc, corr, name, kw, fpb, staging):
     assert rel_l2(mat.cpu().numpy(), V) < TOL, name
 
 
+def test_x_kernels_slice_blocks_alike(xc, corr):
+    """A block large enough for the X stage to pick its slice count by whole
+    rounds of workgroups (2100 frames, 20 inputs, 8 subbands, 1024 channels:
+    four slices of 525 frames rather than three of 700): the ring-fed matrix
+    kernel (the default), the vector ring, the per-wave matrix kernel and the
+    register-staged kernel all cut it alike and give the same bits."""
+    job = configs.small_job("cuda", n_stations=10, n_subbands=8, n_pols=2, n_chan=1024, C=16,
+                            n_frames=2100, seed=77, realistic=True)
+    outs = {}
+    try:
+        for fb in (0, 8, xc.XMAC_MATRIX, 2):
+            corr.set_tuning(xmac_frames_per_stage=fb)
+            outs[fb] = corr.correlate(job, frames_per_block=2100)
+        torch.cuda.synchronize()
+    finally:
+        corr.set_tuning(xmac_frames_per_stage=0)
+    v0, w0 = outs[0]
+    for fb, (v, w) in outs.items():
+        assert torch.equal(w, w0) and torch.equal(v, v0), fb
+
+
 def test_tuning_variants_bit_identical(xc, corr):
     """Launch-shape variants change speed only: visibilities must be bit-identical
     (F-stage variants 1, 3, 4 and the pol-sharing 2 (the dual-pol default) and 8
