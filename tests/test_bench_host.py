@@ -112,3 +112,37 @@ def test_committed_counter_summaries_are_consistent():
         v = json.load(fh)
     assert 20 < v["fstage"]["instr_per_station_sample"] < 100
     assert 0 < v["fstage"]["valu_busy"] <= 1.0
+
+
+class _Shape:
+    """The job fields the block-size rules read (a stand-in for a job)."""
+
+    def __init__(self, n_subbands, M, n_chan, n_frames):
+        self.n_subbands, self.M, self.n_chan, self.n_frames = n_subbands, M, n_chan, n_frames
+
+
+def test_block_size_rules_mirror_the_library():
+    """bench.py's copies of the library's block-size rules (the per-job check
+    of the batch and served results runs each job at the block size the
+    library gives it there): 2048 frames or more while a block's FP32 spectra
+    stay within 16 GiB; in a batch, a 1 GiB bound unless it would cut the job
+    into more than four blocks; in the server, half the budget over the slots
+    (at least 1 GiB), never below 16 (M + 1) frames."""
+    c2 = _Shape(8, 20, 1024, 62500)                      # 1.31 MB of spectra per frame
+    assert bench._default_fpb(c2) == (16 << 30) // (8 * 20 * 1024 * 8) == 13107
+    assert bench._default_fpb(_Shape(1, 2, 256, 31250)) == 31250    # small: one block
+    assert bench._default_fpb(_Shape(16, 20, 8192, 5000)) == 2048    # never below 2048
+    # batch: the 1 GiB bound gives C2 819 frames, 77 blocks: a long job keeps the default
+    assert bench._batch_fpb(c2) == 13107
+    # cut into at most four blocks by the bound: it takes the bounded size
+    mid = _Shape(8, 20, 1024, 3000)
+    assert bench._batch_fpb(mid) == (1 << 30) // (8 * 20 * 1024 * 8) == 819
+    assert -(-mid.n_frames // 819) == 4
+    # a tuned size is bounded the same way
+    assert bench._batch_fpb(mid, tuned_fpb=2048) == 819
+    # server: 96 GiB over 16 slots -> 3 GiB per request
+    assert bench._server_fpb(c2, 96 << 30, 16) == (3 << 30) // (8 * 20 * 1024 * 8) == 2457
+    # a small budget keeps the 1 GiB floor; the 16 (M + 1)-frame floor holds
+    assert bench._server_fpb(c2, 4 << 30, 16) == 819
+    big = _Shape(16, 40, 16384, 2000)                    # 84 MB per frame
+    assert bench._server_fpb(big, 96 << 30, 16) == 16 * 41
