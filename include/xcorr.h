@@ -268,12 +268,14 @@ int xc_get_tuning(const xc_ctx* ctx, xc_tuning* t);
  * recording once), one clear of all accumulators and one finalise serve the
  * whole batch.  Long jobs (their own launches fill the GPU) and jobs the
  * fused kernels do not take (FP16 / FP8 precision, 16384 channels, drift
- * correction, or an X-stage tuning other than the default) run as single jobs
- * on the lanes, longest first.  XC_BATCH_LANES instead runs every
+ * correction, or an X-stage tuning other than the default or the rings) run as
+ * single jobs on the lanes, longest first.  XC_BATCH_LANES instead runs every
  * job as a single job, spread longest-first over the lanes.  Either way the
  * results are identical bit for bit to running each job alone with the
- * batch's block size (the library default, capped so that a job's staged
- * spectra stay within 1 GiB).  With XC_BATCH_GRAPH the launches are captured
+ * batch's block size: the library default, capped so that a job's staged
+ * spectra stay within 1 GiB, except for a job the cap would cut into more than
+ * four blocks, which keeps the default block and runs on the first lane, one
+ * such job after another (so that it gives the same bits as a plain call).  With XC_BATCH_GRAPH the launches are captured
  * once as a hipGraph and a later call with an identical batch replays the
  * graph (one launch). */
 typedef struct {
@@ -302,7 +304,10 @@ int xc_correlate_batch(xc_ctx* ctx, const xc_job* jobs, int32_t n_jobs, int32_t 
  * their work overlaps on the device.  Admission is first-in first-out, except
  * that a later request may start ahead of one that does not fit yet (at most
  * 8 times, then the earlier one blocks admission until it fits).  Results do
- * not depend on what else runs.  Station recordings and outputs stay
+ * not depend on what else runs (a request's block is the library default,
+ * capped so that its staged spectra stay within half the budget over the
+ * slots, at least 1 GiB; never below 16 (M + 1) frames: the request run alone
+ * at that block size gives the same bits).  Station recordings and outputs stay
  * caller-owned device memory and must stay valid until the request is done;
  * the job description (setup, stations, polynomials) is copied at submit. */
 typedef struct xc_server xc_server;
